@@ -1,0 +1,201 @@
+/*
+ * qpx.h -- C-ABI of the batched single-precision differentiable
+ * interior-point QP solver for MI355X (gfx950).
+ *
+ * Each QP in a batch is
+ *
+ *     minimize 1/2 x'Qx + q'x   subject to  A x = b,  G x <= h
+ *
+ * with x in R^n, G in R^{m x n} (m inequality rows), A in R^{p x n}
+ * (p equality rows); paper section 2.1.  Multipliers: z (inequalities),
+ * y (equalities); slacks s = h - Gx.
+ *
+ * Conventions for every entry point
+ *  - All problem, solution and gradient arrays are DEVICE pointers, float32,
+ *    batch-major and row-major (C-contiguous): Q[B][n][n], q[B][n],
+ *    A[B][p][n], b[B][p], G[B][m][n], h[B][m], x[B][n], y[B][p], z[B][m],
+ *    s[B][m].  Per-QP status/iteration arrays are int32[B].
+ *  - The caller owns every buffer it passes.  The library never frees or
+ *    keeps a caller pointer beyond the stream order of the call.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Calls enqueue work and return; results are valid once the stream
+ *    reaches that point.
+ *  - Return value: QPX_OK (0) or a negative QPX_ERR_* code.  Argument errors
+ *    are detected on the host before anything is enqueued.  A per-QP
+ *    numerical failure never fails the call: it is reported in status[].
+ *  - Nothing here allocates per call except qp_solve / qp_backward's
+ *    device workspace, which the context grows on demand and keeps.
+ */
+#ifndef QPX_H
+#define QPX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ------------------------------------------------------ */
+#define QPX_OK 0
+#define QPX_PENDING 1            /* qp_serve_poll: result not ready yet       */
+#define QPX_ERR_ARG (-1)         /* invalid argument (NULL, sizes, options)   */
+#define QPX_ERR_OOM (-2)         /* device or host allocation failed          */
+#define QPX_ERR_HIP (-3)         /* a HIP runtime call failed                 */
+#define QPX_ERR_STATE (-4)       /* object used in the wrong state            */
+#define QPX_ERR_UNSUPPORTED (-5) /* size beyond what the kernels support      */
+
+/* ---- per-QP status (status[i] & 0xff) ----------------------------------- */
+#define QPX_CONVERGED 0    /* scaled KKT residual < tol                       */
+#define QPX_MAX_ITER 1     /* max_iter reached; last iterate returned         */
+#define QPX_NONFINITE 2    /* a non-finite value appeared; see stage          */
+#define QPX_FACTOR_FAIL 3  /* non-positive pivot in the KKT factorisation     */
+/* (status[i] >> 8) & 0xff: first solver stage that produced a non-finite
+ * value or failed factorisation (appendix D.4's trace groups):              */
+#define QPX_STAGE_NONE 0
+#define QPX_STAGE_SCALING 1    /* standard form: z/s scaling                  */
+#define QPX_STAGE_PREDICTOR 2  /* (affine) predictor direction, incl. factor  */
+#define QPX_STAGE_CENTERING 3  /* centering quantities (sigma, mu / kappa)    */
+#define QPX_STAGE_CORRECTOR 4  /* corrector direction                         */
+#define QPX_STAGE_LINESEARCH 5 /* step length                                 */
+#define QPX_STAGE_RELAX 6      /* relaxation to kappa_relax                   */
+#define QPX_STAGE_BACKWARD 7   /* adjoint solve / gradients                   */
+
+/* ---- formulations ------------------------------------------------------- */
+#define QPX_BOUNDED 0   /* implicit complementarity, spectrally bounded system
+                           (section 4, eq. implicit_partially_condensed)      */
+#define QPX_STANDARD 1  /* standard explicit complementarity (section 3,
+                           eq. explicit_partially_condensed); ablation arm    */
+
+typedef struct qpx_ctx qpx_ctx;
+
+typedef struct {
+  int32_t B, n, m, p;   /* batch size and dimensions; m or p may be 0        */
+  const float *Q, *q;   /* Q symmetric positive semidefinite                 */
+  const float *A, *b;   /* may be NULL iff p == 0                            */
+  const float *G, *h;   /* may be NULL iff m == 0                            */
+} qp_batch;
+
+typedef struct {
+  int32_t form;          /* QPX_BOUNDED or QPX_STANDARD                       */
+  int32_t max_iter;      /* Newton iterations of the solve (default 100)      */
+  float tol;             /* stopping tolerance on scaled residuals (1e-5)     */
+  float sigma;           /* fixed centering kappa_target = sigma kappa when
+                            pc == 0 (Algorithm 1 as printed; default 0.1)     */
+  int32_t pc;            /* 1: predictor-corrector centering (default)        */
+  float kappa_relax;     /* central-path parameter of the backward (1e-4)     */
+  int32_t relax_max_iter;/* Newton iterations of the relaxation (50)          */
+  float relax_tol;       /* stopping tolerance of the relaxation (1e-5)       */
+  int32_t kmax;          /* cap on bordered inequality rows of the bounded
+                            factorisation; 0 = automatic (n - p, >= 1)        */
+  float delta_reg;       /* relative Tikhonov floor on the bordered block (0) */
+  int32_t refine_steps;  /* iterative refinement steps of each KKT solve (0)  */
+  int32_t block;         /* threads per QP: 0 = automatic, or 64/128/256/512  */
+} qp_opts;
+
+typedef struct {
+  float *x, *y, *z, *s;  /* [B][n], [B][p], [B][m], [B][m]; y may be NULL iff
+                            p == 0, z and s may be NULL iff m == 0            */
+  int32_t *status;       /* [B] per-QP status (see above); required           */
+  int32_t *iters;        /* [B] Newton iterations used; may be NULL           */
+  float *res;            /* [B] final scaled residual measure; may be NULL    */
+  double *work;          /* [B] algorithmic flops of this QP's solve, counted
+                            from the sizes of each iteration; may be NULL     */
+} qp_out;
+
+typedef struct {
+  float *dQ, *dq, *dA, *db, *dG, *dh; /* same shapes as the problem; any may
+                                         be NULL to skip writing it           */
+} qp_grads;
+
+/* Fill `o` with the defaults listed above.  Returns QPX_OK. */
+int qp_default_opts(qp_opts *o);
+
+/* Create a context bound to HIP device `device` (the device is made current
+ * for the calls made through the context).  Returns QPX_ERR_HIP if the
+ * device does not exist.  *ctx is NULL on failure. */
+int qp_create(qpx_ctx **ctx, int device);
+
+/* Release the context and its workspace.  NULL is accepted.  Work enqueued
+ * through the context must be complete (the call synchronises the device). */
+int qp_destroy(qpx_ctx *ctx);
+
+/* Solve every QP of `batch` (Algorithm 1, implicit complementarity, or the
+ * standard Mehrotra method when opts->form == QPX_STANDARD).  Writes
+ * out->x, y, z, s, status and the optional arrays.  opts == NULL uses the
+ * defaults.  Errors: QPX_ERR_ARG for NULL or inconsistent pointers, B < 0,
+ * n < 1, m < 0, p < 0, p >= n, tol <= 0, max_iter < 1; QPX_ERR_UNSUPPORTED
+ * if the sizes exceed what the kernels handle; QPX_ERR_OOM / QPX_ERR_HIP
+ * from the runtime.  B == 0 is a no-op. */
+int qp_solve(qpx_ctx *ctx, const qp_batch *batch, const qp_opts *opts,
+             qp_out *out, void *stream);
+
+/* Backward pass at the relaxed point (sections 2.3 and 5):
+ *  1. warm-start from the solution (x, y, z, s) given in `sol` (as written
+ *     by qp_solve) and relax to kappa_relax (Algorithm 2);
+ *  2. factor the reduced KKT system at the relaxed point and solve the
+ *     adjoint system for the upstream gradient dl_dx [B][n] (Algorithm 3);
+ *  3. write the parameter gradients dQ (symmetrised), dq, dA, db, dG, dh.
+ * dl_dy [B][p] and dl_dz [B][m] may be NULL (zero upstream).  `relaxed`, if
+ * not NULL, receives the relaxed point (its x, y, z, s, status, iters).
+ * sol->status is read: QPs whose solve did not converge are still relaxed.
+ * Errors as for qp_solve, plus QPX_ERR_ARG if kappa_relax <= 0. */
+int qp_backward(qpx_ctx *ctx, const qp_batch *batch, const qp_opts *opts,
+                const qp_out *sol, const float *dl_dx, const float *dl_dy,
+                const float *dl_dz, qp_grads *grads, qp_out *relaxed,
+                void *stream);
+
+/* Human-readable name of a per-QP status value or return code. */
+const char *qp_status_string(int code);
+
+/* ---- serving: continuous batching of single QPs ------------------------- */
+typedef struct qpx_server qpx_server;
+
+typedef struct {
+  int32_t max_slots;       /* QPs resident on the device at once (256)        */
+  int32_t iters_per_step;  /* Newton iterations per device step (4)           */
+  int32_t n_max;           /* largest n accepted (256)                        */
+  size_t arena_bytes;      /* device arena for resident QPs; admission is by
+                              footprint (0 = 256 MiB)                          */
+} qp_server_opts;
+
+typedef struct {
+  double t_submit, t_admit, t_done; /* seconds on the host monotonic clock    */
+  int32_t status, iters;
+} qp_timing;
+
+/* Create a server that runs a scheduler thread on `ctx`'s device with its
+ * own stream.  `opts`/`solver` may be NULL for defaults. */
+int qp_server_create(qpx_ctx *ctx, const qp_server_opts *opts,
+                     const qp_opts *solver, qpx_server **srv);
+
+/* Submit one QP.  Q..h are HOST pointers (row-major float32, sizes as in
+ * qp_batch with B = 1); they are copied before the call returns.  A/b may be
+ * NULL iff p == 0, G/h iff m == 0.  *ticket identifies the request.
+ * Errors: QPX_ERR_ARG (bad sizes, n > n_max, footprint > arena),
+ * QPX_ERR_STATE (server stopped). */
+int qp_serve_submit(qpx_server *srv, int32_t n, int32_t m, int32_t p,
+                    const float *Q, const float *q, const float *A,
+                    const float *b, const float *G, const float *h,
+                    uint64_t *ticket);
+
+/* Non-blocking.  Returns QPX_PENDING while the request is queued or on the
+ * device; QPX_OK once done, after copying the solution into the HOST
+ * buffers x[n], y[p], z[m], s[m] (any may be NULL) and filling *timing (may
+ * be NULL).  A ticket can be collected once; QPX_ERR_ARG for an unknown or
+ * already collected ticket. */
+int qp_serve_poll(qpx_server *srv, uint64_t ticket, float *x, float *y,
+                  float *z, float *s, qp_timing *timing);
+
+/* Counters: requests admitted / completed, and the peak number of QPs that
+ * were resident on the device together.  Any pointer may be NULL. */
+int qp_serve_stats(qpx_server *srv, uint64_t *admitted, uint64_t *completed,
+                   int32_t *peak_resident);
+
+/* Stop the scheduler (finishing resident work) and free the server. */
+int qp_server_destroy(qpx_server *srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QPX_H */

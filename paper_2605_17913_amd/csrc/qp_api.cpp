@@ -1,0 +1,241 @@
+// Host side of the C-ABI declared in include/qpx.h: argument validation,
+// launch configuration, workspace management.  Every step of the solver runs
+// in the HIP kernels of qp_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+
+#include "../../include/qpx.h"
+#include "qp_internal.h"
+
+struct qpx_ctx {
+  int device = 0;
+  float *ws = nullptr;     // global factor storage, grown on demand
+  size_t ws_bytes = 0;
+  std::mutex mu;           // guards ws growth
+};
+
+namespace {
+
+int set_device(const qpx_ctx *ctx) {
+  return hipSetDevice(ctx->device) == hipSuccess ? QPX_OK : QPX_ERR_HIP;
+}
+
+// Grow the workspace; the previous contents are not kept.  The caller's
+// stream is synchronised before freeing a buffer that may still be in use.
+int ensure_ws(qpx_ctx *ctx, size_t bytes, hipStream_t st) {
+  if (bytes <= ctx->ws_bytes) return QPX_OK;
+  if (ctx->ws) {
+    if (hipDeviceSynchronize() != hipSuccess) return QPX_ERR_HIP;
+    hipFree(ctx->ws);
+    ctx->ws = nullptr;
+    ctx->ws_bytes = 0;
+  }
+  (void)st;
+  void *p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) return QPX_ERR_OOM;
+  ctx->ws = static_cast<float *>(p);
+  ctx->ws_bytes = bytes;
+  return QPX_OK;
+}
+
+struct Plan {
+  int kb = 0;
+  int threads = 256;
+  bool m_in_lds = true;
+  size_t lds = 0;
+  int64_t ws_stride = 0;
+};
+
+constexpr int kMaxN = 512;   // bordered system dimension supported by the kernels
+
+int make_plan(int n, int m, int p, const qp_opts &o, Plan *pl) {
+  int kb = o.kmax > 0 ? o.kmax : std::max(1, n - p);
+  kb = std::min(kb, m);
+  if (o.form == QPX_STANDARD) kb = 0;
+  if (kb < 0) kb = 0;
+  if (n + kb + p > kMaxN) kb = kMaxN - n - p;
+  if (kb < 0 || n + p > kMaxN) return QPX_ERR_UNSUPPORTED;
+  if (m > 4096) return QPX_ERR_UNSUPPORTED;
+  pl->kb = kb;
+  const int N = n + kb + p;
+  int T = o.block;
+  if (T == 0) T = N <= 64 ? 128 : (N <= 256 ? 256 : 512);
+  if (T != 64 && T != 128 && T != 256 && T != 512) return QPX_ERR_ARG;
+  pl->threads = T;
+  const size_t lim = qpk::lds_limit();
+  const size_t with_m = qpk::lds_bytes(n, m, p, kb, true);
+  if (with_m <= lim) {
+    pl->m_in_lds = true;
+    pl->lds = with_m;
+    pl->ws_stride = 0;
+  } else {
+    pl->m_in_lds = false;
+    pl->lds = qpk::lds_bytes(n, m, p, kb, false);
+    if (pl->lds > lim) return QPX_ERR_UNSUPPORTED;
+    pl->ws_stride = qpk::ws_floats(n, m, p, kb);
+  }
+  return QPX_OK;
+}
+
+int check_batch(const qp_batch *bt) {
+  if (!bt) return QPX_ERR_ARG;
+  if (bt->B < 0 || bt->n < 1 || bt->m < 0 || bt->p < 0 || bt->p >= bt->n) return QPX_ERR_ARG;
+  if (bt->B == 0) return QPX_OK;
+  if (!bt->Q || !bt->q) return QPX_ERR_ARG;
+  if (bt->p > 0 && (!bt->A || !bt->b)) return QPX_ERR_ARG;
+  if (bt->m > 0 && (!bt->G || !bt->h)) return QPX_ERR_ARG;
+  return QPX_OK;
+}
+
+int check_opts(const qp_opts &o) {
+  if (o.form != QPX_BOUNDED && o.form != QPX_STANDARD) return QPX_ERR_ARG;
+  if (!(o.tol > 0.f) || o.max_iter < 1 || o.max_iter > 100000) return QPX_ERR_ARG;
+  if (!(o.sigma > 0.f && o.sigma < 1.f)) return QPX_ERR_ARG;
+  if (!(o.delta_reg >= 0.f)) return QPX_ERR_ARG;
+  if (o.kmax < 0 || o.refine_steps < 0) return QPX_ERR_ARG;
+  return QPX_OK;
+}
+
+void fill_common(qpk::Params &P, const qp_batch *bt, const qp_opts &o, const Plan &pl,
+                 qpx_ctx *ctx) {
+  std::memset(&P, 0, sizeof(P));
+  P.B = bt->B; P.n = bt->n; P.m = bt->m; P.p = bt->p;
+  P.Q = bt->Q; P.q = bt->q; P.A = bt->A; P.b = bt->b; P.G = bt->G; P.h = bt->h;
+  P.form = o.form; P.max_iter = o.max_iter; P.pc = o.pc; P.kb = pl.kb;
+  P.relax_max_iter = o.relax_max_iter; P.refine = o.refine_steps;
+  P.tol = o.tol; P.sigma = o.sigma; P.kappa_relax = o.kappa_relax;
+  P.relax_tol = o.relax_tol; P.delta_reg = o.delta_reg;
+  P.ws = pl.m_in_lds ? nullptr : ctx->ws;
+  P.ws_stride = pl.ws_stride;
+}
+
+}  // namespace
+
+extern "C" {
+
+int qp_default_opts(qp_opts *o) {
+  if (!o) return QPX_ERR_ARG;
+  o->form = QPX_BOUNDED;
+  o->max_iter = 100;
+  o->tol = 1e-5f;
+  o->sigma = 0.1f;
+  o->pc = 1;
+  o->kappa_relax = 1e-4f;
+  o->relax_max_iter = 50;
+  o->relax_tol = 1e-5f;
+  o->kmax = 0;
+  o->delta_reg = 0.f;
+  o->refine_steps = 0;
+  o->block = 0;
+  return QPX_OK;
+}
+
+int qp_create(qpx_ctx **ctx, int device) {
+  if (!ctx) return QPX_ERR_ARG;
+  *ctx = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return QPX_ERR_HIP;
+  qpx_ctx *c = new (std::nothrow) qpx_ctx();
+  if (!c) return QPX_ERR_OOM;
+  c->device = device;
+  *ctx = c;
+  return QPX_OK;
+}
+
+int qp_destroy(qpx_ctx *ctx) {
+  if (!ctx) return QPX_OK;
+  hipSetDevice(ctx->device);
+  hipDeviceSynchronize();
+  if (ctx->ws) hipFree(ctx->ws);
+  delete ctx;
+  return QPX_OK;
+}
+
+int qp_solve(qpx_ctx *ctx, const qp_batch *bt, const qp_opts *opts, qp_out *out,
+             void *stream) {
+  if (!ctx || !out) return QPX_ERR_ARG;
+  int rc = check_batch(bt);
+  if (rc) return rc;
+  qp_opts o;
+  if (opts) o = *opts; else qp_default_opts(&o);
+  if ((rc = check_opts(o))) return rc;
+  if (bt->B == 0) return QPX_OK;
+  if (!out->x || !out->status) return QPX_ERR_ARG;
+  if (bt->p > 0 && !out->y) return QPX_ERR_ARG;
+  if (bt->m > 0 && (!out->z || !out->s)) return QPX_ERR_ARG;
+  Plan pl;
+  if ((rc = make_plan(bt->n, bt->m, bt->p, o, &pl))) return rc;
+  if ((rc = set_device(ctx))) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (!pl.m_in_lds) {
+    if ((rc = ensure_ws(ctx, (size_t)bt->B * pl.ws_stride * sizeof(float), st))) return rc;
+  }
+  qpk::Params P;
+  fill_common(P, bt, o, pl, ctx);
+  P.x = out->x; P.y = out->y; P.z = out->z; P.s = out->s;
+  P.status = out->status; P.iters = out->iters; P.res = out->res; P.work = out->work;
+  P.mode = qpk::kSolve;
+  const hipError_t e = qpk::launch(P, pl.threads, pl.m_in_lds, pl.lds, bt->B, st);
+  return e == hipSuccess ? QPX_OK : QPX_ERR_HIP;
+}
+
+int qp_backward(qpx_ctx *ctx, const qp_batch *bt, const qp_opts *opts, const qp_out *sol,
+                const float *dl_dx, const float *dl_dy, const float *dl_dz, qp_grads *grads,
+                qp_out *relaxed, void *stream) {
+  if (!ctx || !sol || !grads) return QPX_ERR_ARG;
+  int rc = check_batch(bt);
+  if (rc) return rc;
+  qp_opts o;
+  if (opts) o = *opts; else qp_default_opts(&o);
+  if ((rc = check_opts(o))) return rc;
+  if (!(o.kappa_relax > 0.f) || !(o.relax_tol > 0.f) || o.relax_max_iter < 0) return QPX_ERR_ARG;
+  if (bt->B == 0) return QPX_OK;
+  if (!dl_dx || !sol->x) return QPX_ERR_ARG;
+  if (bt->p > 0 && !sol->y) return QPX_ERR_ARG;
+  if (bt->m > 0 && (!sol->z || !sol->s)) return QPX_ERR_ARG;
+  Plan pl;
+  if ((rc = make_plan(bt->n, bt->m, bt->p, o, &pl))) return rc;
+  if ((rc = set_device(ctx))) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (!pl.m_in_lds) {
+    if ((rc = ensure_ws(ctx, (size_t)bt->B * pl.ws_stride * sizeof(float), st))) return rc;
+  }
+  qpk::Params P;
+  fill_common(P, bt, o, pl, ctx);
+  P.x = sol->x; P.y = sol->y; P.z = sol->z; P.s = sol->s;
+  P.gx = dl_dx; P.gy = bt->p ? dl_dy : nullptr; P.gz = bt->m ? dl_dz : nullptr;
+  P.dQ = grads->dQ; P.dq = grads->dq; P.dA = grads->dA; P.db = grads->db;
+  P.dG = grads->dG; P.dh = grads->dh;
+  if (relaxed) {
+    P.rx = relaxed->x; P.ry = relaxed->y; P.rz = relaxed->z; P.rs = relaxed->s;
+    P.rstatus = relaxed->status; P.riters = relaxed->iters; P.work = relaxed->work;
+  }
+  P.mode = qpk::kBackward;
+  const hipError_t e = qpk::launch(P, pl.threads, pl.m_in_lds, pl.lds, bt->B, st);
+  return e == hipSuccess ? QPX_OK : QPX_ERR_HIP;
+}
+
+const char *qp_status_string(int code) {
+  switch (code) {
+    case QPX_OK: return "ok / converged";
+    case QPX_PENDING: return "pending / max_iter";
+    case QPX_NONFINITE: return "non-finite value";
+    case QPX_FACTOR_FAIL: return "factorisation failed (non-positive pivot)";
+    case QPX_ERR_ARG: return "invalid argument";
+    case QPX_ERR_OOM: return "out of memory";
+    case QPX_ERR_HIP: return "HIP runtime error";
+    case QPX_ERR_STATE: return "invalid state";
+    case QPX_ERR_UNSUPPORTED: return "unsupported size";
+    default: return "unknown";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,68 @@
+// Internal interface between the host C-ABI (qp_api.cpp) and the HIP
+// kernels (qp_kernels.hip).  Not installed; not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace qpk {
+
+// Kernel modes.
+enum Mode : int32_t {
+  kSolve = 0,     // Algorithm 1 (or the standard IPM): init + Newton loop
+  kBackward = 1,  // relax (Algorithm 2) + adjoint (Algorithm 3) + gradients
+  kServe = 2,     // serving step: resume a resident QP for a few iterations
+};
+
+// Everything a kernel launch needs.  Problem pointers are batch bases;
+// QP i's arrays start at i * (its size).  For serving, `desc` replaces the
+// batch layout (one descriptor per slot).
+struct Params {
+  int32_t B, n, m, p;
+  const float *Q, *q, *A, *b, *G, *h;
+  // outputs of the solve / inputs of the backward
+  float *x, *y, *z, *s;
+  int32_t *status, *iters;
+  float *res;
+  double *work;
+  // backward
+  const float *gx, *gy, *gz;
+  float *dQ, *dq, *dA, *db, *dG, *dh;
+  float *rx, *ry, *rz, *rs;  // relaxed point (optional)
+  int32_t *rstatus, *riters;
+  // options
+  int32_t form, max_iter, pc, kb, relax_max_iter, refine;
+  float tol, sigma, kappa_relax, relax_tol, delta_reg;
+  // factor storage in global memory (when it does not fit LDS)
+  float *ws;
+  int64_t ws_stride;  // floats per QP
+  // serving
+  const struct SlotDesc *desc;
+  int32_t mode;
+};
+
+// One resident serving slot.  All pointers are device pointers into the
+// server's arena; `state` holds x, y, z, s contiguously.
+struct SlotDesc {
+  int32_t n, m, p, flags;   // flags: bit0 = fresh (run the initialisation)
+  const float *Q, *q, *A, *b, *G, *h;
+  float *state;             // x[n] y[p] z[m] s[m]
+  float *ws;                // factor storage (global) or NULL
+  int32_t *status, *iters;  // per slot
+  float *res;
+};
+
+// Bytes of dynamic LDS a launch needs, and whether the factor matrix M
+// lives in LDS.  Returns 0 if the configuration is unsupported.
+size_t lds_bytes(int n, int m, int p, int kb, bool m_in_lds);
+// Floats of global factor storage per QP when M is not in LDS.
+int64_t ws_floats(int n, int m, int p, int kb);
+// Largest dynamic LDS per block the kernels may use on this device.
+size_t lds_limit();
+
+// Launch the fused kernel for `P.mode` with `threads` per block.  Returns a
+// hipError_t.
+hipError_t launch(const Params &P, int threads, bool m_in_lds, size_t lds,
+                  int grid, hipStream_t stream);
+
+}  // namespace qpk

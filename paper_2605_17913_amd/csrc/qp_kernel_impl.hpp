@@ -1,0 +1,1338 @@
+// Kernel templates; included by the per-configuration instantiation units.
+#pragma once
+// Fused batched interior-point kernels for gfx950 (MI355X).
+//
+// One workgroup owns one QP for its whole solve: problem data is read from
+// HBM (it stays L2/MALL resident across iterations), the iterate, residuals
+// and directions live in LDS, and the bordered KKT factor lives in LDS when
+// it fits (else in a per-QP global workspace).  No host synchronisation
+// happens inside a solve; each QP exits its Newton loop on its own.
+//
+// Method (paper section 4): implicit complementarity with the softplus
+// retraction b_kappa (eq. softplus, appendix C).  Each Newton step solves the
+// reduced symmetric system of eq. implicit_partially_condensed
+//
+//     [ Q - G'G   G'      A' ] [dx]     [ r_t - G'(r_i + r_z - r_s) ]
+//     [ G        -B(-v)   0  ] [dv] = - [ r_i - r_s - c r_kappa     ]
+//     [ A         0       0  ] [dy]     [ r_e                       ]
+//
+// The paper only says the matrix is symmetric and admits LDL'; it is
+// indefinite, so it is factored here by a sign-split elimination that is
+// exact in exact arithmetic and needs no pivoting:
+//   * rows with v_i <= 0 (D_i = b'(-v_i) >= 1/2) are eliminated: pivot
+//     -D_i, which folds G_i' (E_i/D_i) G_i into the (1,1) block, with
+//     E_i/D_i = z_i/s_i in (0, 1];
+//   * rows with v_i > 0 are kept as a border with the change of variable
+//     du_i = E_i dv_i, giving the diagonal -D_i/E_i = -s_i/z_i in (-1, 0);
+//   * the equality rows A are kept as a border with a zero diagonal.
+// The result is the quasi-definite matrix
+//
+//     M = [ H   C' ]    H = Q + G_I' diag(E/D) G_I  (positive definite),
+//         [ C  -Dl ]    C = [G_B; A],  Dl = diag(s_B / z_B, 0_p) >= 0,
+//
+// factored as M = L diag(sg) L' with known signs sg = (+1 x n, -1 x k):
+// a Cholesky whose trailing k pivots are negated.  Every multiplier is
+// bounded (E, D in (0,1), E/D <= 1 on eliminated rows, D/E < 1 on border
+// rows), which is the spectral bound the paper relies on.  When more than
+// kb rows have v_i > 0, the kb rows with the largest v are bordered and the
+// rest eliminated (their weight z/s is then > 1 but moderate).
+//
+// The standard (explicit) arm factors the normal matrix Q + G' diag(z/s) G
+// bordered by A (eq. explicit_partially_condensed with dz eliminated) with
+// the same signed Cholesky, and runs Mehrotra's predictor-corrector.
+#include <hip/hip_runtime.h>
+#include <float.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "qp_internal.h"
+
+namespace qpk {
+namespace {
+
+#define QPD __device__ __forceinline__
+
+constexpr int kNB = 16;          // panel width of the blocked factorisation
+constexpr float kBig = 3.0e38f;
+
+// Explicit address spaces: LDS (3) and global (1).  Helpers that are not
+// inlined keep 32-bit LDS addresses and emit ds_* / global_* instructions.
+typedef __attribute__((address_space(3))) float lf;
+typedef __attribute__((address_space(3))) int li;
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) f4v lf4;
+typedef __attribute__((address_space(1))) float gf;
+typedef __attribute__((address_space(1))) f4v gf4;
+template <class F> struct Vec4;
+template <> struct Vec4<lf> { typedef lf4 type; };
+template <> struct Vec4<gf> { typedef gf4 type; };
+template <> struct Vec4<const lf> { typedef const lf4 type; };
+template <> struct Vec4<const gf> { typedef const gf4 type; };
+
+QPD bool finitef(float a) { return fabsf(a) <= FLT_MAX; }
+
+QPD float readlane(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+// Orders LDS / global accesses of one wavefront (lanes exchange data
+// through memory without a workgroup barrier).
+QPD void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+struct OpSum { QPD static float f(float a, float b) { return a + b; } };
+struct OpMax { QPD static float f(float a, float b) { return fmaxf(a, b); } };
+struct OpMin { QPD static float f(float a, float b) { return fminf(a, b); } };
+
+// Reduce K values across the workgroup; every thread gets the results.
+// `red` needs (T/64)*K floats.  Contains two barriers.
+template <int T, class Op, int K>
+QPD void block_reduce(float (&v)[K], lf *red) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v[k] = Op::f(v[k], __shfl_xor(v[k], o, 64));
+  }
+  if constexpr (T > 64) {
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) red[w * K + k] = v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      float r = red[k];
+#pragma unroll
+      for (int i = 1; i < T / 64; ++i) r = Op::f(r, red[i * K + k]);
+      v[k] = r;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Softplus retraction, cancellation-free (appendix C).
+QPD float bk(float v, float kappa) {
+  const float r = sqrtf(fmaf(v, v, 4.f * kappa));
+  return v >= 0.f ? 0.5f * (v + r) : 2.f * kappa / (r - v);
+}
+// b_kappa'(v): (1 + v/r)/2 for v >= 0, 2 kappa / (r^2 - v r) for v < 0.
+QPD float dbk(float v, float kappa, float r) {
+  return v >= 0.f ? 0.5f * (1.f + v / r) : 2.f * kappa / (r * (r - v));
+}
+
+// ---------------------------------------------------------------------------
+// Per-QP LDS layout (floats; ints share the float arena).  All blocks are
+// 4-float aligned.
+struct Layout {
+  int n, m, p, kb, Nmax, ld;
+  int x, y, z, s, v, q, h, b;
+  int E, D, c;
+  int rt, ri, re, rz, rs;
+  int tQ, tGz, tAy;
+  int t0, t1, u0, u1, dv0, dv1, dinv;
+  int part, red;
+  int role, bidx, elist, iflag;
+  int M;      // offset of M if in LDS, else -1
+  int total;  // floats
+};
+
+__host__ __device__ inline int al4(int a) { return (a + 3) & ~3; }
+
+__host__ __device__ inline Layout make_layout(int n, int m, int p, int kb, bool m_lds) {
+  Layout L;
+  L.n = n; L.m = m; L.p = p; L.kb = kb;
+  L.Nmax = n + kb + p;
+  L.ld = al4(L.Nmax);
+  int o = 0;
+  auto take = [&](int cnt) { int r = o; o += al4(cnt > 0 ? cnt : 1); return r; };
+  L.x = take(n); L.y = take(p); L.z = take(m); L.s = take(m); L.v = take(m);
+  L.q = take(n); L.h = take(m); L.b = take(p);
+  L.E = take(m); L.D = take(m); L.c = take(m);
+  L.rt = take(n); L.ri = take(m); L.re = take(p); L.rz = take(m); L.rs = take(m);
+  L.tQ = take(n); L.tGz = take(n); L.tAy = take(n);
+  L.t0 = take(m > p ? m : p); L.t1 = take(m > p ? m : p);
+  L.u0 = take(L.Nmax); L.u1 = take(L.Nmax);
+  L.dv0 = take(m); L.dv1 = take(m); L.dinv = take(L.Nmax);
+  L.part = take(1024); L.red = take(16 * 32);
+  L.role = take(m); L.bidx = take(m); L.elist = take(m); L.iflag = take(16);
+  if (m_lds) { L.M = o; o += L.Nmax * L.ld + 4; } else { L.M = -1; }
+  L.total = o;
+  return L;
+}
+
+// ---------------------------------------------------------------------------
+// Dense helpers on one workgroup of T threads.
+
+// out[i] = sum_j R[i*ld + j] x[j] for i < rows (16 lanes per row).
+template <int T, int NV, class RF>
+QPD void rowdot(const RF *R, int ld, int rows, int cols, const lf *const (&x)[NV],
+                lf *const (&out)[NV]) {
+  const int sub = threadIdx.x & 15, grp = threadIdx.x >> 4;
+  for (int i0 = 0; i0 < rows; i0 += T / 16) {
+    const int i = i0 + grp;
+    float acc[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) acc[k] = 0.f;
+    if (i < rows) {
+      const RF *Ri = R + (size_t)i * ld;
+      for (int j = sub; j < cols; j += 16) {
+        const float r = Ri[j];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) acc[k] = fmaf(r, x[k][j], acc[k]);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+#pragma unroll
+      for (int o = 8; o > 0; o >>= 1) acc[k] += __shfl_xor(acc[k], o, 16);
+    }
+    if (sub == 0 && i < rows) {
+#pragma unroll
+      for (int k = 0; k < NV; ++k) out[k][i] = acc[k];
+    }
+  }
+}
+
+// out[j] = sum_i R[i*ld + j] x[i] for j < cols.  Threads split the rows in
+// groups and combine partial sums through `part` (T floats).  Contains
+// barriers; `x` must be visible to all threads on entry.
+template <int T, int NV, class RF>
+QPD void coldot(const RF *R, int ld, int rows, int cols, const lf *const (&x)[NV],
+                lf *const (&out)[NV], lf *part) {
+  static_assert(NV * T <= 1024, "part too small");
+  const int cw = cols <= 64 ? 64 : (cols <= 128 ? (T >= 128 ? 128 : 64) : (T >= 256 ? 256 : T));
+  const int groups = T / cw;
+  const int g = threadIdx.x / cw, jl = threadIdx.x % cw;
+  for (int jb = 0; jb < cols; jb += cw) {
+    const int j = jb + jl;
+    float acc[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) acc[k] = 0.f;
+    if (j < cols) {
+      for (int i = g; i < rows; i += groups) {
+        const float r = R[(size_t)i * ld + j];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) acc[k] = fmaf(r, x[k][i], acc[k]);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < NV; ++k) part[k * T + threadIdx.x] = acc[k];
+    __syncthreads();
+    if (g == 0 && j < cols) {
+#pragma unroll
+      for (int k = 0; k < NV; ++k) {
+        float s = 0.f;
+        for (int gg = 0; gg < groups; ++gg) s += part[k * T + gg * cw + jl];
+        out[k][j] = s;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// In-place M = L diag(sg) L' (lower triangle, row-major, leading dim ld),
+// sg_j = +1 for j < npos, -1 otherwise.  Blocked right-looking: one wave
+// factors each NB-wide panel in registers (lane = row), then the whole
+// workgroup applies the rank-NB update to the trailing lower triangle in
+// 4x4 register tiles.  The strict upper triangle receives a copy of L'
+// (M[j][i] = L[i][j]) so both triangular solves walk contiguous rows.
+// Returns false (uniformly) if a pivot sg_j * a_jj is not a positive
+// finite number.  RPL = rows per lane, >= ceil(N / 64).
+template <int T, class MF>
+__device__ __noinline__ bool signed_cholesky(MF *M, int ld, int N, int npos, li *flag) {
+  typedef typename Vec4<const MF>::type V4;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  if (tid == 0) *flag = 0;
+  __syncthreads();
+  for (int k0 = 0; k0 < N; k0 += kNB) {
+    const int kb = min(kNB, N - k0);
+    if (wid == 0) {
+      // panel columns k0 .. k0+kb-1 by one wave, in place in M
+      bool fail = false;
+      for (int jj = 0; jj < kb; ++jj) {
+        const int j = k0 + jj;
+        const float sg = j < npos ? 1.f : -1.f;
+        const float tt = sg * M[(size_t)j * ld + j];
+        const bool ok = tt > 0.f && tt <= FLT_MAX;
+        fail |= !ok;
+        const float d = ok ? sqrtf(tt) : 1.f;
+        const float inv = sg / d;
+        wave_sync();
+        if (lane == 0) M[(size_t)j * ld + j] = d;
+        for (int i = j + 1 + lane; i < N; i += 64) {
+          const float l = M[(size_t)i * ld + j] * inv;
+          M[(size_t)i * ld + j] = l;
+          M[(size_t)j * ld + i] = l;  // copy of L' in the upper triangle
+        }
+        wave_sync();
+        for (int cc = jj + 1; cc < kb; ++cc) {
+          const int col = k0 + cc;
+          const float lc = M[(size_t)j * ld + col] * sg;  // L[col][j] sg_j (upper copy)
+          for (int i = col + lane; i < N; i += 64)
+            M[(size_t)i * ld + col] = fmaf(-M[(size_t)i * ld + j], lc, M[(size_t)i * ld + col]);
+        }
+        wave_sync();
+      }
+      if (fail && lane == 0) *flag = 1;
+    }
+    __syncthreads();
+    // trailing update of rows/cols [r0, N): M -= Lp diag(sg_p) Lp'
+    const int r0 = k0 + kb, R = N - r0;
+    if (R > 0) {
+      const int nt = (R + 3) >> 2;
+      const int ntiles = nt * (nt + 1) / 2;
+      for (int t = tid; t < ntiles; t += T) {
+        int ti = (int)((sqrtf(8.f * (float)t + 1.f) - 1.f) * 0.5f);
+        while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+        while (ti * (ti + 1) / 2 > t) --ti;
+        const int tj = t - ti * (ti + 1) / 2;
+        const int i0 = r0 + 4 * ti, j0 = r0 + 4 * tj;
+        float acc[4][4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int bq = 0; bq < 4; ++bq) acc[a][bq] = 0.f;
+#pragma unroll 1
+        for (int c = 0; c < kNB; c += 4) {
+          f4v av[4], bv[4];
+#pragma unroll
+          for (int a = 0; a < 4; ++a) {
+            const int ia = min(i0 + a, N - 1), ja = min(j0 + a, N - 1);
+            av[a] = *reinterpret_cast<V4 *>(M + (size_t)ia * ld + k0 + c);
+            bv[a] = *reinterpret_cast<V4 *>(M + (size_t)ja * ld + k0 + c);
+          }
+          const float s0 = (k0 + c + 0) < npos ? 1.f : -1.f;
+          const float s1 = (k0 + c + 1) < npos ? 1.f : -1.f;
+          const float s2 = (k0 + c + 2) < npos ? 1.f : -1.f;
+          const float s3 = (k0 + c + 3) < npos ? 1.f : -1.f;
+#pragma unroll
+          for (int bq = 0; bq < 4; ++bq) {
+            bv[bq].x *= s0; bv[bq].y *= s1; bv[bq].z *= s2; bv[bq].w *= s3;
+          }
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int bq = 0; bq < 4; ++bq) {
+              float r = acc[a][bq];
+              r = fmaf(av[a].x, bv[bq].x, r);
+              r = fmaf(av[a].y, bv[bq].y, r);
+              r = fmaf(av[a].z, bv[bq].z, r);
+              r = fmaf(av[a].w, bv[bq].w, r);
+              acc[a][bq] = r;
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          const int i = i0 + a;
+          if (i < N) {
+#pragma unroll
+            for (int bq = 0; bq < 4; ++bq) {
+              const int j = j0 + bq;
+              if (j <= i) M[(size_t)i * ld + j] -= acc[a][bq];
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  return *flag == 0;
+}
+
+// Solve (L diag(sg) L') u = r in place for one right-hand side held in
+// `r` (length N), by a single wave with the vector in registers (lane owns
+// rows lane + 64 t).  Uses the L' copy in the strict upper triangle for the
+// forward sweep and L's rows for the backward sweep; dinv[j] = 1 / L[j][j].
+template <int RPL, class MF>
+QPD void signed_solve_wave(const MF *M, int ld, int N, int npos, const lf *dinv, lf *r) {
+  const int lane = threadIdx.x & 63;
+  float a[RPL];
+#pragma unroll
+  for (int t = 0; t < RPL; ++t) {
+    const int i = lane + 64 * t;
+    a[t] = i < N ? r[i] : 0.f;
+  }
+  // forward: L w = r
+  for (int j = 0; j < N; ++j) {
+    const int tj = j >> 6, lj = j & 63;
+    float rj = 0.f;
+#pragma unroll
+    for (int t = 0; t < RPL; ++t)
+      if (t == tj) rj = readlane(a[t], lj);
+    const float wj = rj * dinv[j];
+    const MF *Lr = M + (size_t)j * ld;  // L[i][j] = M[j][i] for i > j
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) {
+      const int i = lane + 64 * t;
+      if (i > j && i < N) a[t] = fmaf(-Lr[i], wj, a[t]);
+      if (i == j) a[t] = wj;
+    }
+  }
+  // sign: w <- sg w
+#pragma unroll
+  for (int t = 0; t < RPL; ++t) {
+    const int i = lane + 64 * t;
+    if (i >= npos) a[t] = -a[t];
+  }
+  // backward: L' u = w
+  for (int j = N - 1; j >= 0; --j) {
+    const int tj = j >> 6, lj = j & 63;
+    float rj = 0.f;
+#pragma unroll
+    for (int t = 0; t < RPL; ++t)
+      if (t == tj) rj = readlane(a[t], lj);
+    const float uj = rj * dinv[j];
+    const MF *Lr = M + (size_t)j * ld;  // L[j][i] for i < j
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) {
+      const int i = lane + 64 * t;
+      if (i < j) a[t] = fmaf(-Lr[i], uj, a[t]);
+      if (i == j) a[t] = uj;
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < RPL; ++t) {
+    const int i = lane + 64 * t;
+    if (i < N) r[i] = a[t];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The per-QP context: LDS views plus this QP's global problem data.
+template <class MF>
+struct Ctx {
+  typedef MF MT;
+  Layout L;
+  int n, m, p, kb;
+  const gf *Q, *q_g, *A, *b_g, *G, *h_g;
+  lf *sm;    // LDS arena
+  MF *M;     // factor storage (LDS or global)
+  int ld;
+  lf *x, *y, *z, *s, *v, *q, *h, *b;
+  lf *E, *D, *c;
+  lf *rt, *ri, *re, *rz, *rs;
+  lf *tQ, *tGz, *tAy;
+  lf *t0, *t1, *u0, *u1, *dv0, *dv1, *dinv;
+  lf *part, *red;
+  li *role, *bidx, *elist, *iflag;
+};
+
+template <class MF>
+QPD void init_ctx(Ctx<MF> &C, lf *sm, const Layout &L, MF *Mptr) {
+  C.L = L; C.n = L.n; C.m = L.m; C.p = L.p; C.kb = L.kb;
+  C.sm = sm;
+  C.M = Mptr;
+  C.ld = L.ld;
+  C.x = sm + L.x; C.y = sm + L.y; C.z = sm + L.z; C.s = sm + L.s; C.v = sm + L.v;
+  C.q = sm + L.q; C.h = sm + L.h; C.b = sm + L.b;
+  C.E = sm + L.E; C.D = sm + L.D; C.c = sm + L.c;
+  C.rt = sm + L.rt; C.ri = sm + L.ri; C.re = sm + L.re; C.rz = sm + L.rz; C.rs = sm + L.rs;
+  C.tQ = sm + L.tQ; C.tGz = sm + L.tGz; C.tAy = sm + L.tAy;
+  C.t0 = sm + L.t0; C.t1 = sm + L.t1; C.u0 = sm + L.u0; C.u1 = sm + L.u1;
+  C.dv0 = sm + L.dv0; C.dv1 = sm + L.dv1; C.dinv = sm + L.dinv;
+  C.part = sm + L.part; C.red = sm + L.red;
+  C.role = reinterpret_cast<li *>(sm + L.role);
+  C.bidx = reinterpret_cast<li *>(sm + L.bidx);
+  C.elist = reinterpret_cast<li *>(sm + L.elist);
+  C.iflag = reinterpret_cast<li *>(sm + L.iflag);
+}
+
+// Residuals at (x, y, z, s) and, for the bounded form, (v, kappa).
+// Returns the scaled residual measure (uniform); `bad` = a non-finite value
+// was seen.  complementarity: max(z s) (solve) or max|z s - kr| / kr (relax).
+template <int T, class CT>
+__device__ __noinline__ float residuals(CT &C, bool bounded, float kappa, float kr, bool *bad) {
+  const int n = C.n, m = C.m, p = C.p, tid = threadIdx.x;
+  {
+    const lf *xv[1] = {C.x};
+    lf *o1[1] = {C.t0};
+    if (m) rowdot<T, 1>(C.G, n, m, n, xv, o1);
+    lf *o2[1] = {C.re};
+    if (p) rowdot<T, 1>(C.A, n, p, n, xv, o2);
+  }
+  {
+    const lf *xv[1] = {C.x};
+    lf *o[1] = {C.tQ};
+    coldot<T, 1>(C.Q, n, n, n, xv, o, C.part);
+    if (m) {
+      const lf *zv[1] = {C.z};
+      lf *o2[1] = {C.tGz};
+      coldot<T, 1>(C.G, n, m, n, zv, o2, C.part);
+    }
+    if (p) {
+      const lf *yv[1] = {C.y};
+      lf *o3[1] = {C.tAy};
+      coldot<T, 1>(C.A, n, p, n, yv, o3, C.part);
+    }
+  }
+  // max-norm accumulators
+  enum { RT, QX, QQ, GZ, AY, RI, GX, SS, HH, RE, AX, BB, RZS, ZZ, CC, NF, NK };
+  float mx[NK];
+#pragma unroll
+  for (int k = 0; k < NK; ++k) mx[k] = 0.f;
+  for (int i = tid; i < n; i += T) {
+    const float gz = m ? C.tGz[i] : 0.f, ay = p ? C.tAy[i] : 0.f;
+    const float r = C.tQ[i] + C.q[i] + gz + ay;
+    C.rt[i] = r;
+    mx[RT] = fmaxf(mx[RT], fabsf(r));
+    mx[QX] = fmaxf(mx[QX], fabsf(C.tQ[i]));
+    mx[QQ] = fmaxf(mx[QQ], fabsf(C.q[i]));
+    mx[GZ] = fmaxf(mx[GZ], fabsf(gz));
+    mx[AY] = fmaxf(mx[AY], fabsf(ay));
+    if (!finitef(r)) mx[NF] = 1.f;
+  }
+  for (int i = tid; i < m; i += T) {
+    const float gx = C.t0[i], si = C.s[i], zi = C.z[i];
+    const float r = gx + si - C.h[i];
+    C.ri[i] = r;
+    mx[RI] = fmaxf(mx[RI], fabsf(r));
+    mx[GX] = fmaxf(mx[GX], fabsf(gx));
+    mx[SS] = fmaxf(mx[SS], fabsf(si));
+    mx[HH] = fmaxf(mx[HH], fabsf(C.h[i]));
+    mx[ZZ] = fmaxf(mx[ZZ], fabsf(zi));
+    float rz = 0.f, rs = 0.f;
+    if (bounded) {
+      const float vi = C.v[i];
+      rz = zi - bk(vi, kappa);
+      rs = si - bk(-vi, kappa);
+      C.rz[i] = rz;
+      C.rs[i] = rs;
+    }
+    mx[RZS] = fmaxf(mx[RZS], fmaxf(fabsf(rz), fabsf(rs)));
+    const float zs = zi * si;
+    mx[CC] = fmaxf(mx[CC], kr > 0.f ? fabsf(zs - kr) / kr : zs);
+    if (!finitef(r) || !finitef(zs) || !finitef(rz) || !finitef(rs)) mx[NF] = 1.f;
+  }
+  for (int i = tid; i < p; i += T) {
+    const float ax = C.re[i];
+    const float r = ax - C.b[i];
+    C.re[i] = r;
+    mx[RE] = fmaxf(mx[RE], fabsf(r));
+    mx[AX] = fmaxf(mx[AX], fabsf(ax));
+    mx[BB] = fmaxf(mx[BB], fabsf(C.b[i]));
+    if (!finitef(r)) mx[NF] = 1.f;
+  }
+  block_reduce<T, OpMax, NK>(mx, C.red);
+  const float rt_s = mx[RT] / (1.f + fmaxf(fmaxf(mx[QX], mx[QQ]), fmaxf(mx[GZ], mx[AY])));
+  const float ri_s = m ? mx[RI] / (1.f + fmaxf(mx[GX], fmaxf(mx[SS], mx[HH]))) : 0.f;
+  const float re_s = p ? mx[RE] / (1.f + fmaxf(mx[AX], mx[BB])) : 0.f;
+  const float rzs = m ? mx[RZS] / (1.f + fmaxf(mx[ZZ], mx[SS])) : 0.f;
+  const float cc = m ? mx[CC] : 0.f;
+  *bad = mx[NF] != 0.f;
+  return fmaxf(fmaxf(rt_s, ri_s), fmaxf(fmaxf(re_s, rzs), cc));
+}
+
+// Workgroup-wide exclusive compaction of rows with flag set, in row order.
+// Writes the compacted indices to out[] and returns the count (uniform).
+template <int T>
+QPD int compact_rows(const li *flag, int m, li *out, lf *red) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  int base = 0;
+  for (int i0 = 0; i0 < m; i0 += T) {
+    const int i = i0 + tid;
+    const bool f = i < m && flag[i];
+    const unsigned long long bal = __ballot(f);
+    const int pre = __popcll(bal & ((1ull << lane) - 1ull));
+    const int wcnt = __popcll(bal);
+    li *wsum = reinterpret_cast<li *>(red);
+    if (lane == 0) wsum[w] = wcnt;
+    __syncthreads();
+    int off = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < T / 64; ++k) {
+      const int c = wsum[k];
+      off += k < w ? c : 0;
+      tot += c;
+    }
+    if (f) out[base + off + pre] = i;
+    base += tot;
+    __syncthreads();
+  }
+  return base;
+}
+
+// Bounded form: retraction derivatives and the sign split.  Returns the
+// number of bordered rows nb; fills E, D, c, role (border index or -1),
+// bidx (border rows), elist (eliminated rows) and iflag[1] = #eliminated.
+template <int T, class CT>
+__device__ __noinline__ int partition_bounded(CT &C, float kappa) {
+  const int m = C.m, tid = threadIdx.x;
+  li *cand = C.role;  // temporarily: candidate flags
+  float cnt[1] = {0.f};
+  for (int i = tid; i < m; i += T) {
+    const float vi = C.v[i];
+    const float r = sqrtf(fmaf(vi, vi, 4.f * kappa));
+    C.E[i] = dbk(vi, kappa, r);
+    C.D[i] = dbk(-vi, kappa, r);
+    C.c[i] = 1.f / r;
+    const int f = vi > 0.f;
+    cand[i] = f;
+    cnt[0] += (float)f;
+  }
+  block_reduce<T, OpSum, 1>(cnt, C.red);
+  const int ncand = (int)cnt[0];
+  if (ncand > C.kb) {
+    // keep the kb largest v (ties by row index)
+    li *keep = C.elist;  // scratch flags
+    for (int i = tid; i < m; i += T) {
+      int f = 0;
+      if (cand[i]) {
+        const float vi = C.v[i];
+        int rank = 0;
+        for (int j = 0; j < m; ++j) {
+          const float vj = C.v[j];
+          rank += (vj > vi) || (vj == vi && j < i);
+        }
+        f = rank < C.kb;
+      }
+      keep[i] = f;
+    }
+    __syncthreads();
+    for (int i = tid; i < m; i += T) cand[i] = keep[i];
+  }
+  __syncthreads();
+  const int nb = compact_rows<T>(cand, m, C.bidx, C.red);
+  // eliminated rows = not bordered
+  for (int i = tid; i < m; i += T) cand[i] = !cand[i];
+  __syncthreads();
+  const int ne = compact_rows<T>(cand, m, C.elist, C.red);
+  for (int i = tid; i < m; i += T) C.role[i] = -1;
+  __syncthreads();
+  for (int k = tid; k < nb; k += T) C.role[C.bidx[k]] = k;
+  if (tid == 0) C.iflag[1] = ne;
+  __syncthreads();
+  return nb;
+}
+
+// Assemble M = [[H, C'], [C, -Dl]] (lower triangle) for N = n + nb + p.
+// H = Q + sum_{r in elist} w_r g_r g_r' with w = weights (E/D bounded,
+// z/s standard); border rows = G[bidx] then A; Dl = dl (per border row) and
+// delta on the diagonal of the border block.
+template <int T, class CT>
+__device__ __noinline__ void assemble(CT &C, int nb, int ne, const lf *wts, bool bounded, float delta) {
+  const int n = C.n, p = C.p, tid = threadIdx.x, ld = C.ld;
+  auto *M = C.M;
+  // H block in 4x4 tiles
+  const int nt = (n + 3) >> 2;
+  const int ntiles = nt * (nt + 1) / 2;
+  for (int t = tid; t < ntiles; t += T) {
+    int ti = (int)((sqrtf(8.f * (float)t + 1.f) - 1.f) * 0.5f);
+    while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+    while (ti * (ti + 1) / 2 > t) --ti;
+    const int tj = t - ti * (ti + 1) / 2;
+    const int i0 = 4 * ti, j0 = 4 * tj;
+    float acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int bq = 0; bq < 4; ++bq) {
+        const int i = min(i0 + a, n - 1), j = min(j0 + bq, n - 1);
+        acc[a][bq] = C.Q[(size_t)i * n + j];
+      }
+#pragma unroll 2
+    for (int k = 0; k < ne; ++k) {
+      const int r = C.elist[k];
+      const float w = wts[r];
+      const gf *gr = C.G + (size_t)r * n;
+      float gi[4], gj[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        gi[a] = gr[min(i0 + a, n - 1)];
+        gj[a] = w * gr[min(j0 + a, n - 1)];
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int bq = 0; bq < 4; ++bq) acc[a][bq] = fmaf(gi[a], gj[bq], acc[a][bq]);
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int i = i0 + a;
+      if (i < n) {
+#pragma unroll
+        for (int bq = 0; bq < 4; ++bq) {
+          const int j = j0 + bq;
+          if (j <= i) M[(size_t)i * ld + j] = acc[a][bq];
+        }
+      }
+    }
+  }
+  // border rows: [C | -Dl (lower part)]
+  const int K = nb + p;
+  for (int e = tid; e < K * (n + K); e += T) {
+    const int k = e / (n + K), col = e % (n + K);
+    const int row = n + k;
+    if (col > row) continue;
+    float val;
+    if (col < n) {
+      val = k < nb ? C.G[(size_t)C.bidx[k] * n + col] : C.A[(size_t)(k - nb) * n + col];
+    } else {
+      const int l = col - n;
+      if (l != k) {
+        val = 0.f;
+      } else {
+        float dl = 0.f;
+        if (k < nb && bounded) {
+          const int r = C.bidx[k];
+          dl = C.D[r] / C.E[r];
+        }
+        val = -(dl + delta);
+      }
+    }
+    M[(size_t)row * ld + col] = val;
+  }
+  __syncthreads();
+}
+
+// dinv[j] = 1 / L[j][j]
+template <int T, class CT>
+QPD void make_dinv(CT &C, int N) {
+  for (int j = threadIdx.x; j < N; j += T) C.dinv[j] = 1.f / C.M[(size_t)j * C.ld + j];
+  __syncthreads();
+}
+
+// Solve for both right-hand sides u0 and u1 (wave 0 and wave 1 in parallel
+// when the workgroup has two waves).
+template <int T, int RPL, class CT>
+__device__ __noinline__ void solve2(CT &C, int N, bool both) {
+  const int wid = threadIdx.x >> 6;
+  if constexpr (T >= 128) {
+    if (wid == 0) signed_solve_wave<RPL>(C.M, C.ld, N, C.n, C.dinv, C.u0);
+    else if (wid == 1 && both) signed_solve_wave<RPL>(C.M, C.ld, N, C.n, C.dinv, C.u1);
+  } else {
+    signed_solve_wave<RPL>(C.M, C.ld, N, C.n, C.dinv, C.u0);
+    if (both) signed_solve_wave<RPL>(C.M, C.ld, N, C.n, C.dinv, C.u1);
+  }
+  __syncthreads();
+}
+
+// Bounded-form right-hand sides of the augmented system for two columns:
+//   column 0: rho = (r_t - G'(r_i + r_z - r_s), r_i - r_s - c (kappa - kt0), r_e)
+//   column 1: rho = (0, c, 0)   (derivative with respect to kappa_target)
+// or, for the adjoint (mode adj): column 0 rho = (gx, E gz, gy), no column 1.
+// With psi_i = rho2_i / D_i on eliminated rows and rho2_i on border rows:
+//   u = [ -rho1 - G' psi ;  -rho2_B ;  -rho3 ].
+// rho2 of each column is left in dv0 / dv1 for the recovery.
+template <int T, class CT>
+__device__ __noinline__ void rhs_bounded(CT &C, int nb, float kappa, const gf *gx, const gf *gz,
+                     const gf *gy, bool adj) {
+  const int n = C.n, m = C.m, p = C.p, tid = threadIdx.x;
+  // phi0 = -(r_i + r_z - r_s) + psi0 would give u_x = -r_t - G' phi0;
+  // we compute w0 = (r_i + r_z - r_s) - psi0 so u_x = -r_t + G' w0, and
+  // w1 = -psi1 so u_x1 = G' w1.
+  for (int i = tid; i < m; i += T) {
+    const bool border = C.role[i] >= 0;
+    float r2a, w0, w1 = 0.f;
+    if (!adj) {
+      r2a = C.ri[i] - C.rs[i] - C.c[i] * kappa;
+      const float psi0 = border ? r2a : r2a / C.D[i];
+      w0 = (C.ri[i] + C.rz[i] - C.rs[i]) - psi0;
+      const float r2b = C.c[i];
+      const float psi1 = border ? r2b : r2b / C.D[i];
+      w1 = -psi1;
+      C.dv1[i] = r2b;
+    } else {
+      r2a = gz ? C.E[i] * gz[i] : 0.f;
+      const float psi0 = border ? r2a : r2a / C.D[i];
+      w0 = -psi0;
+    }
+    C.dv0[i] = r2a;
+    C.t0[i] = w0;
+    C.t1[i] = w1;
+  }
+  __syncthreads();
+  if (m) {
+    if (!adj) {
+      const lf *xv[2] = {C.t0, C.t1};
+      lf *o[2] = {C.tGz, C.tAy};
+      coldot<T, 2>(C.G, n, m, n, xv, o, C.part);
+    } else {
+      const lf *xv[1] = {C.t0};
+      lf *o[1] = {C.tGz};
+      coldot<T, 1>(C.G, n, m, n, xv, o, C.part);
+    }
+  }
+  for (int i = tid; i < n; i += T) {
+    const float g0 = m ? C.tGz[i] : 0.f;
+    if (!adj) {
+      C.u0[i] = -C.rt[i] + g0;
+      C.u1[i] = m ? C.tAy[i] : 0.f;
+    } else {
+      C.u0[i] = -gx[i] + g0;
+    }
+  }
+  for (int k = tid; k < nb; k += T) {
+    const int r = C.bidx[k];
+    C.u0[n + k] = -C.dv0[r];
+    if (!adj) C.u1[n + k] = -C.dv1[r];
+  }
+  for (int k = tid; k < p; k += T) {
+    C.u0[n + nb + k] = adj ? (gy ? -gy[k] : 0.f) : -C.re[k];
+    if (!adj) C.u1[n + nb + k] = 0.f;
+  }
+  __syncthreads();
+}
+
+// Recover dv for the solved columns: eliminated rows dv = (G dx + rho2)/D,
+// border rows dv = du / E.  rho2 is read from dv0 / dv1 and overwritten.
+template <int T, class CT>
+__device__ __noinline__ void recover_bounded(CT &C, int nb, bool both) {
+  const int n = C.n, m = C.m, tid = threadIdx.x;
+  if (!m) return;
+  if (both) {
+    const lf *xv[2] = {C.u0, C.u1};
+    lf *o[2] = {C.t0, C.t1};
+    rowdot<T, 2>(C.G, n, m, n, xv, o);
+  } else {
+    const lf *xv[1] = {C.u0};
+    lf *o[1] = {C.t0};
+    rowdot<T, 1>(C.G, n, m, n, xv, o);
+  }
+  __syncthreads();
+  for (int i = tid; i < m; i += T) {
+    const int k = C.role[i];
+    if (k >= 0) {
+      const float ie = 1.f / C.E[i];
+      C.dv0[i] = C.u0[n + k] * ie;
+      if (both) C.dv1[i] = C.u1[n + k] * ie;
+    } else {
+      const float id = 1.f / C.D[i];
+      C.dv0[i] = (C.t0[i] + C.dv0[i]) * id;
+      if (both) C.dv1[i] = (C.t1[i] + C.dv1[i]) * id;
+    }
+  }
+  __syncthreads();
+}
+
+// Ratio test of eq. linesearch over (s, ds), (z, dz); returns the min of the
+// ratios (uninclusive of the cap 1).
+QPD float ratio(float s, float ds) { return ds < 0.f ? -s / ds : kBig; }
+
+constexpr int ST_CONV = 0, ST_MAXIT = 1, ST_NONFIN = 2, ST_FACT = 3;
+constexpr int SG_NONE = 0, SG_SCAL = 1, SG_PRED = 2, SG_CENT = 3, SG_CORR = 4, SG_LS = 5,
+              SG_RELAX = 6, SG_BWD = 7;
+
+QPD int mkstatus(int st, int stage) { return st | (stage << 8); }
+
+// ---------------------------------------------------------------------------
+// Initialisation (CVXOPT convention): solve [[Q+G'G, A'], [A, 0]] [x; y] =
+// [-q + G'h; b], zt = Gx - h, s = -zt, z = zt, each shifted positive.
+template <int T, int RPL, class CT>
+__device__ __noinline__ bool initialize(CT &C, double &work) {
+  const int n = C.n, m = C.m, p = C.p, tid = threadIdx.x;
+  for (int i = tid; i < m; i += T) C.E[i] = 1.f;  // unit weights
+  for (int i = tid; i < m; i += T) C.role[i] = 1;
+  __syncthreads();
+  const int ne = compact_rows<T>(C.role, m, C.elist, C.red);
+  assemble<T>(C, 0, ne, C.E, false, 0.f);
+  const int N = n + p;
+  const bool ok = signed_cholesky<T>(C.M, C.ld, N, n, C.iflag);
+  make_dinv<T>(C, N);
+  if (m) {
+    const lf *hv[1] = {C.h};
+    lf *o[1] = {C.tGz};
+    coldot<T, 1>(C.G, n, m, n, hv, o, C.part);
+  }
+  for (int i = tid; i < n; i += T) C.u0[i] = -C.q[i] + (m ? C.tGz[i] : 0.f);
+  for (int k = tid; k < p; k += T) C.u0[n + k] = C.b[k];
+  __syncthreads();
+  solve2<T, RPL>(C, N, false);
+  for (int i = tid; i < n; i += T) C.x[i] = C.u0[i];
+  for (int k = tid; k < p; k += T) C.y[k] = C.u0[n + k];
+  __syncthreads();
+  if (m) {
+    const lf *xv[1] = {C.x};
+    lf *o[1] = {C.t0};
+    rowdot<T, 1>(C.G, n, m, n, xv, o);
+    __syncthreads();
+    float mx[2] = {-kBig, -kBig};
+    for (int i = tid; i < m; i += T) {
+      const float zt = C.t0[i] - C.h[i];
+      C.s[i] = -zt;
+      C.z[i] = zt;
+      mx[0] = fmaxf(mx[0], zt);    // max(-s)
+      mx[1] = fmaxf(mx[1], -zt);   // max(-z)
+    }
+    block_reduce<T, OpMax, 2>(mx, C.red);
+    for (int i = tid; i < m; i += T) {
+      if (mx[0] >= 0.f) C.s[i] += 1.f + mx[0];
+      if (mx[1] >= 0.f) C.z[i] += 1.f + mx[1];
+    }
+  }
+  __syncthreads();
+  const double dn = n, dm = m, dN = N;
+  work += dm * dn * (dn + 1.0) + dN * dN * dN / 3.0 + 2.0 * dN * dN + 4.0 * dm * dn;
+  return ok;
+}
+
+// One Newton iteration of the bounded (implicit) form.  Mode of the target:
+// kt_mode 0 = predictor-corrector, 1 = fixed sigma, 2 = relax (kt = kr).
+// Returns a status code (ST_CONV meaning "keep going"), with the stage in
+// *stage on failure.  Updates x, y, v, kappa, z, s.
+template <int T, int RPL, class CT>
+__device__ __noinline__ int newton_bounded(CT &C, float &kappa, int kt_mode, float sigma, float kr,
+                       float delta_reg, double &work, int *stage) {
+  const int n = C.n, m = C.m, p = C.p, tid = threadIdx.x;
+  const int nb = partition_bounded<T>(C, kappa);
+  const int ne = C.iflag[1];
+  // weights E/D for eliminated rows (stored in t1 temporarily)
+  for (int i = tid; i < m; i += T) C.t1[i] = C.E[i] / C.D[i];
+  __syncthreads();
+  const int N = n + nb + p;
+  assemble<T>(C, nb, ne, C.t1, true, delta_reg);
+  const bool ok = signed_cholesky<T>(C.M, C.ld, N, n, C.iflag);
+  const double dn = n, dm = m, dp = p, dN = N;
+  work += 2.0 * dn * dn + 4.0 * dm * dn + 4.0 * dp * dn;            // residuals
+  work += (double)ne * dn * (dn + 1.0) + dN * dN * dN / 3.0;        // assembly + factor
+  work += 2.0 * (2.0 * dN * dN + 4.0 * dm * dn);                    // two solves
+  if (!ok) { *stage = SG_PRED; return ST_FACT; }
+  make_dinv<T>(C, N);
+  rhs_bounded<T>(C, nb, kappa, nullptr, nullptr, nullptr, false);
+  solve2<T, RPL>(C, N, true);
+  recover_bounded<T>(C, nb, true);
+  // predictor step length (kappa_target = 0) and kappa_aff
+  float kt;
+  if (kt_mode == 0) {
+    float mn[2] = {1.f, 0.f};
+    for (int i = tid; i < m; i += T) {
+      const float dv = C.dv0[i];
+      const float dz = -C.rz[i] + C.E[i] * dv - C.c[i] * kappa;
+      const float ds = -C.rs[i] - C.D[i] * dv - C.c[i] * kappa;
+      mn[0] = fminf(mn[0], fminf(ratio(C.s[i], ds), ratio(C.z[i], dz)));
+      if (!finitef(dz) || !finitef(ds)) mn[1] = -1.f;
+    }
+    block_reduce<T, OpMin, 2>(mn, C.red);
+    if (mn[1] < 0.f) { *stage = SG_PRED; return ST_NONFIN; }
+    const float aa = mn[0];
+    float sm[1] = {0.f};
+    for (int i = tid; i < m; i += T) {
+      const float dv = C.dv0[i];
+      const float dz = -C.rz[i] + C.E[i] * dv - C.c[i] * kappa;
+      const float ds = -C.rs[i] - C.D[i] * dv - C.c[i] * kappa;
+      sm[0] += (C.s[i] + aa * ds) * (C.z[i] + aa * dz);
+    }
+    block_reduce<T, OpSum, 1>(sm, C.red);
+    const float kaff = sm[0] / (float)m;
+    const float ratio_k = kaff / kappa;
+    const float sg = ratio_k * ratio_k * ratio_k;
+    kt = sg * kappa;
+    if (!finitef(kt)) { *stage = SG_CENT; return ST_NONFIN; }
+    kt = fmaxf(kt, 1e-12f);  // keep the central-path parameter positive
+  } else if (kt_mode == 1) {
+    kt = sigma * kappa;
+  } else {
+    kt = kr;
+  }
+  // combined direction and its step length
+  const float dk = kt - kappa;
+  float mn[2] = {1.f, 0.f};
+  for (int i = tid; i < m; i += T) {
+    const float dv = fmaf(kt, C.dv1[i], C.dv0[i]);
+    const float dz = -C.rz[i] + C.E[i] * dv + C.c[i] * dk;
+    const float ds = -C.rs[i] - C.D[i] * dv + C.c[i] * dk;
+    mn[0] = fminf(mn[0], fminf(ratio(C.s[i], ds), ratio(C.z[i], dz)));
+    if (!finitef(dz) || !finitef(ds)) mn[1] = -1.f;
+  }
+  block_reduce<T, OpMin, 2>(mn, C.red);
+  if (mn[1] < 0.f) { *stage = kt_mode == 2 ? SG_RELAX : SG_CORR; return ST_NONFIN; }
+  const float alpha = mn[0];
+  if (!(alpha > 0.f)) { *stage = SG_LS; return ST_NONFIN; }
+  // step on (x, y, v, kappa), then retract z, s
+  for (int i = tid; i < n; i += T) C.x[i] += alpha * fmaf(kt, C.u1[i], C.u0[i]);
+  for (int k = tid; k < p; k += T) C.y[k] += alpha * fmaf(kt, C.u1[n + nb + k], C.u0[n + nb + k]);
+  const float knew = kappa + alpha * dk;
+  for (int i = tid; i < m; i += T) {
+    const float vn = C.v[i] + alpha * fmaf(kt, C.dv1[i], C.dv0[i]);
+    C.v[i] = vn;
+    C.z[i] = bk(vn, knew);
+    C.s[i] = bk(-vn, knew);
+  }
+  kappa = knew;
+  __syncthreads();
+  return ST_CONV;
+}
+
+// One Mehrotra predictor-corrector iteration of the standard form.
+template <int T, int RPL, class CT>
+__device__ __noinline__ int newton_standard(CT &C, float mu, int kt_mode, float kr, float delta_reg, double &work,
+                        int *stage) {
+  const int n = C.n, m = C.m, p = C.p, tid = threadIdx.x;
+  float bad[1] = {0.f};
+  for (int i = tid; i < m; i += T) {
+    const float w = C.z[i] / C.s[i];
+    C.t1[i] = w;
+    C.role[i] = 1;
+    if (!finitef(w)) bad[0] = 1.f;
+  }
+  block_reduce<T, OpMax, 1>(bad, C.red);
+  if (bad[0] != 0.f) { *stage = SG_SCAL; return ST_NONFIN; }
+  const int ne = compact_rows<T>(C.role, m, C.elist, C.red);
+  // the weights t1 must survive: copy to E (unused in the standard form)
+  for (int i = tid; i < m; i += T) C.E[i] = C.t1[i];
+  __syncthreads();
+  const int N = n + p;
+  assemble<T>(C, 0, ne, C.E, false, delta_reg);
+  const bool ok = signed_cholesky<T>(C.M, C.ld, N, n, C.iflag);
+  const double dn = n, dm = m, dp = p, dN = N;
+  work += 2.0 * dn * dn + 4.0 * dm * dn + 4.0 * dp * dn;
+  work += dm * dn * (dn + 1.0) + dN * dN * dN / 3.0;
+  work += 2.0 * (2.0 * dN * dN + 4.0 * dm * dn);
+  if (!ok) { *stage = SG_PRED; return ST_FACT; }
+  make_dinv<T>(C, N);
+  // rhs for a given r_c / s =: q_i;  u_x = -r_t - G'(w r_i - q), u_y = -r_e
+  // then dz = w (r_i + G dx) - q, ds = -r_i - G dx
+  auto rhs_and_solve = [&](const lf *qv) {
+    for (int i = tid; i < m; i += T) C.t0[i] = C.E[i] * C.ri[i] - qv[i];
+    __syncthreads();
+    {
+      const lf *xv[1] = {C.t0};
+      lf *o[1] = {C.tGz};
+      if (m) coldot<T, 1>(C.G, n, m, n, xv, o, C.part);
+    }
+    for (int i = tid; i < n; i += T) C.u0[i] = -C.rt[i] - (m ? C.tGz[i] : 0.f);
+    for (int k = tid; k < p; k += T) C.u0[n + k] = -C.re[k];
+    __syncthreads();
+    solve2<T, RPL>(C, N, false);
+    const lf *xv[1] = {C.u0};
+    lf *o[1] = {C.t0};
+    if (m) rowdot<T, 1>(C.G, n, m, n, xv, o);
+    __syncthreads();
+  };
+  float sgm;
+  if (kt_mode == 2) {
+    // relax: r_c = z s - kr  =>  q = z - kr / s
+    for (int i = tid; i < m; i += T) C.dv1[i] = C.z[i] - kr / C.s[i];
+    __syncthreads();
+    rhs_and_solve(C.dv1);
+  } else {
+    // affine predictor: q = z
+    rhs_and_solve(C.z);
+    float mn[2] = {1.f, 0.f};
+    for (int i = tid; i < m; i += T) {
+      const float gdx = C.t0[i];
+      const float dz = C.E[i] * (C.ri[i] + gdx) - C.z[i];
+      const float ds = -C.ri[i] - gdx;
+      C.dv0[i] = dz;
+      C.dv1[i] = ds;
+      mn[0] = fminf(mn[0], fminf(ratio(C.s[i], ds), ratio(C.z[i], dz)));
+      if (!finitef(dz) || !finitef(ds)) mn[1] = -1.f;
+    }
+    block_reduce<T, OpMin, 2>(mn, C.red);
+    if (mn[1] < 0.f) { *stage = SG_PRED; return ST_NONFIN; }
+    const float aa = mn[0];
+    float sm[1] = {0.f};
+    for (int i = tid; i < m; i += T)
+      sm[0] += (C.s[i] + aa * C.dv1[i]) * (C.z[i] + aa * C.dv0[i]);
+    block_reduce<T, OpSum, 1>(sm, C.red);
+    const float muaff = sm[0] / (float)m;
+    const float rr = muaff / mu;
+    sgm = rr * rr * rr;
+    if (!finitef(sgm) || !finitef(mu)) { *stage = SG_CENT; return ST_NONFIN; }
+    // corrector: r_c = z s + ds_a dz_a - sigma mu  =>  q = z + (ds_a dz_a - sigma mu)/s
+    for (int i = tid; i < m; i += T)
+      C.dv1[i] = C.z[i] + (C.dv1[i] * C.dv0[i] - sgm * mu) / C.s[i];
+    __syncthreads();
+    rhs_and_solve(C.dv1);
+    if (kt_mode == 1) { /* fixed sigma is not used by the standard arm */ }
+  }
+  float mn[2] = {kBig, 0.f};
+  for (int i = tid; i < m; i += T) {
+    const float gdx = C.t0[i];
+    const float dz = C.E[i] * (C.ri[i] + gdx) - C.dv1[i];
+    const float ds = -C.ri[i] - gdx;
+    C.dv0[i] = dz;
+    C.dv1[i] = ds;
+    mn[0] = fminf(mn[0], fminf(ratio(C.s[i], ds), ratio(C.z[i], dz)));
+    if (!finitef(dz) || !finitef(ds)) mn[1] = -1.f;
+  }
+  block_reduce<T, OpMin, 2>(mn, C.red);
+  if (mn[1] < 0.f) { *stage = kt_mode == 2 ? SG_RELAX : SG_CORR; return ST_NONFIN; }
+  const float alpha = fminf(1.f, 0.99f * mn[0]);
+  if (!(alpha > 0.f) || !finitef(alpha)) { *stage = SG_LS; return ST_NONFIN; }
+  for (int i = tid; i < n; i += T) C.x[i] += alpha * C.u0[i];
+  for (int k = tid; k < p; k += T) C.y[k] += alpha * C.u0[n + k];
+  for (int i = tid; i < m; i += T) {
+    C.z[i] += alpha * C.dv0[i];
+    C.s[i] += alpha * C.dv1[i];
+  }
+  __syncthreads();
+  return ST_CONV;
+}
+
+// Newton loop shared by the solve, the relaxation and the serving step.
+// Returns the final status; iters counts Newton steps taken.
+template <int T, int RPL, class CT>
+QPD int newton_loop(CT &C, bool bounded, int max_iter, float tol, int kt_mode, float sigma,
+                    float kr, float delta_reg, double &work, int &iters, float &res) {
+  const int m = C.m, tid = threadIdx.x;
+  int status = ST_MAXIT;
+  int stage = SG_NONE;
+  for (int it = 0;; ++it) {
+    // manifold coordinates v = z - s, kappa = s'z / m
+    float sm[1] = {0.f};
+    for (int i = tid; i < m; i += T) {
+      sm[0] += C.s[i] * C.z[i];
+      if (bounded) C.v[i] = C.z[i] - C.s[i];
+    }
+    block_reduce<T, OpSum, 1>(sm, C.red);
+    float kappa = m ? sm[0] / (float)m : 0.f;
+    bool bad = false;
+    res = residuals<T>(C, bounded, kappa, kt_mode == 2 ? kr : 0.f, &bad);
+    if (bad || !finitef(res)) {
+      status = ST_NONFIN;
+      stage = kt_mode == 2 ? SG_RELAX : (it == 0 ? SG_NONE : SG_LS);
+      iters = it;
+      break;
+    }
+    if (res < tol) { status = ST_CONV; iters = it; break; }
+    if (it >= max_iter || m == 0) { status = ST_MAXIT; iters = it; break; }
+    int st;
+    if (bounded) st = newton_bounded<T, RPL>(C, kappa, kt_mode, sigma, kr, delta_reg, work, &stage);
+    else st = newton_standard<T, RPL>(C, kappa, kt_mode, kr, delta_reg, work, &stage);
+    if (st != ST_CONV) { status = st; iters = it + 1; break; }
+  }
+  return mkstatus(status, stage);
+}
+
+// Load this QP's small vectors into LDS.
+template <int T, class CT>
+QPD void load_vectors(CT &C) {
+  const int tid = threadIdx.x;
+  for (int i = tid; i < C.n; i += T) C.q[i] = C.q_g[i];
+  for (int i = tid; i < C.m; i += T) C.h[i] = C.h_g[i];
+  for (int i = tid; i < C.p; i += T) C.b[i] = C.b_g[i];
+  __syncthreads();
+}
+
+// Factor at the current (relaxed) point and solve the adjoint system for
+// the upstream gradient; returns dx in u0[0:n], dy in u0[n+nb:], dz in dv0.
+template <int T, int RPL, class CT>
+__device__ __noinline__ bool adjoint(CT &C, bool bounded, const gf *gx, const gf *gy, const gf *gz,
+                 float delta_reg, double &work) {
+  const int n = C.n, m = C.m, p = C.p, tid = threadIdx.x;
+  float sm[1] = {0.f};
+  for (int i = tid; i < m; i += T) {
+    sm[0] += C.s[i] * C.z[i];
+    if (bounded) C.v[i] = C.z[i] - C.s[i];
+  }
+  block_reduce<T, OpSum, 1>(sm, C.red);
+  const float kappa = m ? sm[0] / (float)m : 0.f;
+  int nb = 0, ne = 0;
+  if (bounded && m) {
+    nb = partition_bounded<T>(C, kappa);
+    ne = C.iflag[1];
+    for (int i = tid; i < m; i += T) C.t1[i] = C.E[i] / C.D[i];
+  } else {
+    for (int i = tid; i < m; i += T) {
+      C.t1[i] = C.z[i] / C.s[i];
+      C.role[i] = 1;
+    }
+    __syncthreads();
+    ne = compact_rows<T>(C.role, m, C.elist, C.red);
+    for (int i = tid; i < m; i += T) C.role[i] = -1;
+  }
+  __syncthreads();
+  // keep the weights: E holds E (bounded) or z/s (standard)
+  if (!bounded)
+    for (int i = tid; i < m; i += T) C.E[i] = C.t1[i];
+  __syncthreads();
+  const int N = n + nb + p;
+  assemble<T>(C, nb, ne, C.t1, bounded, delta_reg);
+  const bool ok = signed_cholesky<T>(C.M, C.ld, N, n, C.iflag);
+  const double dn = n, dN = N;
+  work += (double)ne * dn * (dn + 1.0) + dN * dN * dN / 3.0 + 2.0 * dN * dN + 8.0 * m * dn;
+  if (!ok) return false;
+  make_dinv<T>(C, N);
+  if (bounded) {
+    rhs_bounded<T>(C, nb, kappa, gx, gz, gy, true);
+    solve2<T, RPL>(C, N, false);
+    recover_bounded<T>(C, nb, false);
+    // dz = E (dv + gz)
+    for (int i = tid; i < m; i += T) C.dv0[i] = C.E[i] * (C.dv0[i] + (gz ? gz[i] : 0.f));
+  } else {
+    // standard: [H A'; A 0][a; c] = [-gx - G' W gz; -gy], dz = W (G a + gz)
+    for (int i = tid; i < m; i += T) C.t0[i] = gz ? C.E[i] * gz[i] : 0.f;
+    __syncthreads();
+    if (m) {
+      const lf *xv[1] = {C.t0};
+      lf *o[1] = {C.tGz};
+      coldot<T, 1>(C.G, n, m, n, xv, o, C.part);
+    }
+    for (int i = tid; i < n; i += T) C.u0[i] = -gx[i] - (m ? C.tGz[i] : 0.f);
+    for (int k = tid; k < p; k += T) C.u0[n + k] = gy ? -gy[k] : 0.f;
+    __syncthreads();
+    solve2<T, RPL>(C, N, false);
+    if (m) {
+      const lf *xv[1] = {C.u0};
+      lf *o[1] = {C.t0};
+      rowdot<T, 1>(C.G, n, m, n, xv, o);
+    }
+    __syncthreads();
+    for (int i = tid; i < m; i += T) C.dv0[i] = C.E[i] * (C.t0[i] + (gz ? gz[i] : 0.f));
+  }
+  // move dy next to dx: u0[n : n+p] = dy
+  __syncthreads();
+  if (nb) {
+    float tmp[4];
+    for (int k0 = 0; k0 < p; k0 += 4 * T) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int k = k0 + tid + u * T;
+        tmp[u] = k < p ? C.u0[n + nb + k] : 0.f;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int k = k0 + tid + u * T;
+        if (k < p) C.u0[n + k] = tmp[u];
+      }
+      __syncthreads();
+    }
+  }
+  return true;
+}
+
+// Write the parameter gradients of Algorithm 3 with coalesced stores.
+template <int T, class CT>
+__device__ __noinline__ void write_grads(CT &C, const Params &P, size_t qi) {
+  const int n = C.n, m = C.m, p = C.p, tid = threadIdx.x;
+  const lf *dx = C.u0, *dy = C.u0 + n, *dz = C.dv0;
+  if (P.dQ) {
+    gf *o = (gf *)P.dQ + qi * (size_t)n * n;
+    for (int e = tid; e < n * n; e += T) {
+      const int i = e / n, j = e % n;
+      o[e] = 0.5f * (dx[i] * C.x[j] + C.x[i] * dx[j]);
+    }
+  }
+  if (P.dq) {
+    gf *o = (gf *)P.dq + qi * (size_t)n;
+    for (int i = tid; i < n; i += T) o[i] = dx[i];
+  }
+  if (P.dA && p) {
+    gf *o = (gf *)P.dA + qi * (size_t)p * n;
+    for (int e = tid; e < p * n; e += T) {
+      const int i = e / n, j = e % n;
+      o[e] = dy[i] * C.x[j] + C.y[i] * dx[j];
+    }
+  }
+  if (P.db && p) {
+    gf *o = (gf *)P.db + qi * (size_t)p;
+    for (int i = tid; i < p; i += T) o[i] = -dy[i];
+  }
+  if (P.dG && m) {
+    gf *o = (gf *)P.dG + qi * (size_t)m * n;
+    for (int e = tid; e < m * n; e += T) {
+      const int i = e / n, j = e % n;
+      o[e] = dz[i] * C.x[j] + C.z[i] * dx[j];
+    }
+  }
+  if (P.dh && m) {
+    gf *o = (gf *)P.dh + qi * (size_t)m;
+    for (int i = tid; i < m; i += T) o[i] = -dz[i];
+  }
+}
+
+// ---------------------------------------------------------------------------
+template <int T, int RPL, bool MLDS>
+__global__ void __launch_bounds__(T, (T >= 256 ? 2 : 4)) qp_kernel(Params P) {
+  extern __shared__ __attribute__((aligned(16))) float smem[];
+  typedef typename std::conditional<MLDS, lf, gf>::type MF;
+  const int n = P.n, m = P.m, p = P.p;
+  const Layout L = make_layout(n, m, p, P.kb, MLDS);
+  const size_t qi = blockIdx.x;
+  lf *sm = (lf *)smem;
+  MF *Mp;
+  if constexpr (MLDS) Mp = sm + L.M;
+  else Mp = (gf *)P.ws + (size_t)qi * P.ws_stride;
+  Ctx<MF> C;
+  init_ctx(C, sm, L, Mp);
+  C.Q = (const gf *)P.Q + qi * (size_t)n * n;
+  C.q_g = (const gf *)P.q + qi * (size_t)n;
+  C.A = p ? (const gf *)P.A + qi * (size_t)p * n : nullptr;
+  C.b_g = p ? (const gf *)P.b + qi * (size_t)p : nullptr;
+  C.G = m ? (const gf *)P.G + qi * (size_t)m * n : nullptr;
+  C.h_g = m ? (const gf *)P.h + qi * (size_t)m : nullptr;
+  const int tid = threadIdx.x;
+  const bool bounded = P.form == 0;
+  load_vectors<T>(C);
+  double work = 0.0;
+  int iters = 0;
+  float res = 0.f;
+  int status;
+  if (P.mode == kSolve) {
+    const bool ok = initialize<T, RPL>(C, work);
+    if (!ok) {
+      status = mkstatus(ST_FACT, SG_PRED);
+      res = __int_as_float(0x7fc00000);
+    } else {
+      status = newton_loop<T, RPL>(C, bounded, P.max_iter, P.tol, P.pc ? 0 : 1, P.sigma, 0.f,
+                                   P.delta_reg, work, iters, res);
+    }
+    gf *xo = (gf *)P.x + qi * (size_t)n;
+    for (int i = tid; i < n; i += T) xo[i] = C.x[i];
+    if (p && P.y) for (int k = tid; k < p; k += T) ((gf *)P.y)[qi * p + k] = C.y[k];
+    if (m && P.z) for (int i = tid; i < m; i += T) ((gf *)P.z)[qi * m + i] = C.z[i];
+    if (m && P.s) for (int i = tid; i < m; i += T) ((gf *)P.s)[qi * m + i] = C.s[i];
+    if (tid == 0) {
+      P.status[qi] = status;
+      if (P.iters) P.iters[qi] = iters;
+      if (P.res) P.res[qi] = res;
+      if (P.work) P.work[qi] = work;
+    }
+  } else {
+    // backward: warm start from the solution
+    const gf *xs = (const gf *)P.x, *ys = (const gf *)P.y, *zs = (const gf *)P.z,
+             *ss = (const gf *)P.s;
+    for (int i = tid; i < n; i += T) C.x[i] = xs[qi * n + i];
+    for (int k = tid; k < p; k += T) C.y[k] = ys[qi * p + k];
+    for (int i = tid; i < m; i += T) {
+      C.z[i] = zs[qi * m + i];
+      C.s[i] = ss[qi * m + i];
+    }
+    __syncthreads();
+    status = newton_loop<T, RPL>(C, bounded, P.relax_max_iter, P.relax_tol, 2, 0.f, P.kappa_relax,
+                                 P.delta_reg, work, iters, res);
+    const gf *gx = (const gf *)P.gx + qi * (size_t)n;
+    const gf *gy = P.gy ? (const gf *)P.gy + qi * (size_t)p : nullptr;
+    const gf *gz = P.gz ? (const gf *)P.gz + qi * (size_t)m : nullptr;
+    const bool ok = adjoint<T, RPL>(C, bounded, gx, gy, gz, P.delta_reg, work);
+    if (!ok) status = mkstatus(ST_FACT, SG_BWD);
+    __syncthreads();
+    write_grads<T>(C, P, qi);
+    if (P.rx) for (int i = tid; i < n; i += T) ((gf *)P.rx)[qi * n + i] = C.x[i];
+    if (P.ry && p) for (int k = tid; k < p; k += T) ((gf *)P.ry)[qi * p + k] = C.y[k];
+    if (P.rz && m) for (int i = tid; i < m; i += T) ((gf *)P.rz)[qi * m + i] = C.z[i];
+    if (P.rs && m) for (int i = tid; i < m; i += T) ((gf *)P.rs)[qi * m + i] = C.s[i];
+    if (tid == 0) {
+      if (P.rstatus) P.rstatus[qi] = status;
+      if (P.riters) P.riters[qi] = iters;
+      if (P.work) P.work[qi] = work;
+    }
+  }
+}
+
+}  // namespace
+
+template <int T, int RPL>
+hipError_t launch_t(const Params &P, bool m_in_lds, size_t lds, int grid, hipStream_t st) {
+  if (m_in_lds) {
+    auto k = qp_kernel<T, RPL, true>;
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(T), lds, st, P);
+  } else {
+    auto k = qp_kernel<T, RPL, false>;
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(T), lds, st, P);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace qpk

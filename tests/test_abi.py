@@ -1,0 +1,60 @@
+"""CPU-side checks of the C-ABI library: it loads, it exports every symbol
+that include/qpx.h declares, and host-side argument validation rejects bad
+calls before anything would reach a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2605_17913_amd as qpx
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qpx.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(qp_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ["qp_solve", "qp_backward", "qp_serve_submit", "qp_serve_poll"]:
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = qpx.lib()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+    assert set(declared_functions()) == set(qpx.EXPORTS)
+
+
+def test_default_opts():
+    o = qpx.default_opts()
+    assert o.form == 0 and o.max_iter == 100 and abs(o.tol - 1e-5) < 1e-12
+    assert o.pc == 1 and abs(o.sigma - 0.1) < 1e-7 and abs(o.kappa_relax - 1e-4) < 1e-10
+
+
+def test_null_arguments_are_rejected_on_the_host():
+    L = qpx.lib()
+    o = qpx.default_opts()
+    bt = qpx._Batch(4, 3, 2, 1, None, None, None, None, None, None)
+    out = qpx._Out()
+    # NULL context
+    assert L.qp_solve(None, ctypes.byref(bt), ctypes.byref(o), ctypes.byref(out), None) == -1
+    assert L.qp_backward(None, ctypes.byref(bt), ctypes.byref(o), ctypes.byref(out), None, None,
+                         None, ctypes.byref(qpx._Grads()), None, None) == -1
+    h = ctypes.c_void_p()
+    assert L.qp_create(None, 0) == -1
+    assert L.qp_status_string(-5) == b"unsupported size"
+    assert L.qp_destroy(None) == 0
+
+
+def test_cpu_tensors_raise():
+    import torch
+    Q = torch.eye(3).unsqueeze(0)
+    with pytest.raises(qpx.QPError):
+        qpx.solve(Q, torch.zeros(1, 3), None, None, None, None)
