@@ -84,10 +84,13 @@ typedef struct {
                             pc == 0 (Algorithm 1 as printed; default 0.1)     */
   int32_t pc;            /* 1: predictor-corrector centering (default)        */
   float kappa_relax;     /* central-path parameter of the backward (1e-4)     */
-  int32_t relax_max_iter;/* Newton iterations of the relaxation (50)          */
-  float relax_tol;       /* stopping tolerance of the relaxation (1e-5)       */
+  int32_t relax_max_iter;/* Newton iterations of the relaxation (30)          */
+  float relax_tol;       /* stopping tolerance of the relaxation (1e-7); the
+                            residuals are accumulated in FP64, and the
+                            gradient of a near-degenerate QP needs a relaxed
+                            point tighter than the solve's tolerance         */
   int32_t kmax;          /* cap on bordered inequality rows of the bounded
-                            factorisation; 0 = automatic (n - p, >= 1)        */
+                            factorisation; 0 = automatic (n)                  */
   float delta_reg;       /* relative Tikhonov floor on the bordered block (0) */
   int32_t refine_steps;  /* iterative refinement steps of each KKT solve (0)  */
   int32_t block;         /* threads per QP: 0 = automatic, or 64/128/256/512  */

@@ -55,7 +55,7 @@ struct Plan {
 constexpr int kMaxN = 512;   // bordered system dimension supported by the kernels
 
 int make_plan(int n, int m, int p, const qp_opts &o, Plan *pl) {
-  int kb = o.kmax > 0 ? o.kmax : std::max(1, n - p);
+  int kb = o.kmax > 0 ? o.kmax : n;
   kb = std::min(kb, m);
   if (o.form == QPX_STANDARD) kb = 0;
   if (kb < 0) kb = 0;
@@ -127,8 +127,8 @@ int qp_default_opts(qp_opts *o) {
   o->sigma = 0.1f;
   o->pc = 1;
   o->kappa_relax = 1e-4f;
-  o->relax_max_iter = 50;
-  o->relax_tol = 1e-5f;
+  o->relax_max_iter = 30;
+  o->relax_tol = 1e-7f;
   o->kmax = 0;
   o->delta_reg = 0.f;
   o->refine_steps = 0;

@@ -60,6 +60,7 @@ constexpr float kBig = 3.0e38f;
 // inlined keep 32-bit LDS addresses and emit ds_* / global_* instructions.
 typedef __attribute__((address_space(3))) float lf;
 typedef __attribute__((address_space(3))) int li;
+typedef __attribute__((address_space(3))) double ldd;
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) f4v lf4;
 typedef __attribute__((address_space(1))) float gf;
@@ -137,6 +138,8 @@ struct Layout {
   int tQ, tGz, tAy;
   int t0, t1, u0, u1, dv0, dv1, dinv;
   int part, red;
+  int w0, w1, rr, dd;  // rhs copies / residual for refinement; FP64 scratch
+  int pan;             // panel staging buffer (factor in global memory)
   int role, bidx, elist, iflag;
   int M;      // offset of M if in LDS, else -1
   int total;  // floats
@@ -160,6 +163,9 @@ __host__ __device__ inline Layout make_layout(int n, int m, int p, int kb, bool 
   L.u0 = take(L.Nmax); L.u1 = take(L.Nmax);
   L.dv0 = take(m); L.dv1 = take(m); L.dinv = take(L.Nmax);
   L.part = take(1024); L.red = take(16 * 32);
+  L.w0 = take(L.Nmax); L.w1 = take(L.Nmax); L.rr = take(L.Nmax);
+  L.dd = take(2 * (2 * m + p + 3 * n + 8));
+  L.pan = m_lds ? take(4) : take(L.Nmax * kNB + 16);
   L.role = take(m); L.bidx = take(m); L.elist = take(m); L.iflag = take(16);
   if (m_lds) { L.M = o; o += L.Nmax * L.ld + 4; } else { L.M = -1; }
   L.total = o;
@@ -245,44 +251,73 @@ QPD void coldot(const RF *R, int ld, int rows, int cols, const lf *const (&x)[NV
 // Returns false (uniformly) if a pivot sg_j * a_jj is not a positive
 // finite number.  RPL = rows per lane, >= ceil(N / 64).
 template <int T, class MF>
-__device__ __noinline__ bool signed_cholesky(MF *M, int ld, int N, int npos, li *flag) {
-  typedef typename Vec4<const MF>::type V4;
+__device__ __noinline__ bool signed_cholesky(MF *M, int ld, int N, int npos, li *flag, lf *pan) {
+  constexpr bool kLds = std::is_same<MF, lf>::value;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   if (tid == 0) *flag = 0;
   __syncthreads();
   for (int k0 = 0; k0 < N; k0 += kNB) {
     const int kb = min(kNB, N - k0);
+    // The panel (rows k0..N-1, columns k0..k0+kb-1) is factored in LDS: in
+    // place when M is in LDS, else in the staging buffer `pan` (row stride
+    // kNB).  Element (i, c) of the panel lives at pb[(i - k0) * pld + c].
+    lf *pb;
+    int pld;
+    if constexpr (kLds) {
+      pb = M + (size_t)k0 * ld + k0;
+      pld = ld;
+    } else {
+      pb = pan;
+      pld = kNB;
+      for (int e = tid; e < (N - k0) * kNB; e += T) {
+        const int r = e / kNB, c = e % kNB;
+        pan[e] = c < kb ? M[(size_t)(k0 + r) * ld + k0 + c] : 0.f;
+      }
+      __syncthreads();
+    }
     if (wid == 0) {
-      // panel columns k0 .. k0+kb-1 by one wave, in place in M
       bool fail = false;
       for (int jj = 0; jj < kb; ++jj) {
         const int j = k0 + jj;
         const float sg = j < npos ? 1.f : -1.f;
-        const float tt = sg * M[(size_t)j * ld + j];
+        const float tt = sg * pb[jj * pld + jj];
         const bool ok = tt > 0.f && tt <= FLT_MAX;
         fail |= !ok;
         const float d = ok ? sqrtf(tt) : 1.f;
         const float inv = sg / d;
         wave_sync();
-        if (lane == 0) M[(size_t)j * ld + j] = d;
+        if (lane == 0) pb[jj * pld + jj] = d;
         for (int i = j + 1 + lane; i < N; i += 64) {
-          const float l = M[(size_t)i * ld + j] * inv;
-          M[(size_t)i * ld + j] = l;
-          M[(size_t)j * ld + i] = l;  // copy of L' in the upper triangle
+          const float l = pb[(i - k0) * pld + jj] * inv;
+          pb[(i - k0) * pld + jj] = l;
+          if constexpr (kLds) M[(size_t)j * ld + i] = l;  // copy of L' in the upper triangle
         }
         wave_sync();
         for (int cc = jj + 1; cc < kb; ++cc) {
-          const int col = k0 + cc;
-          const float lc = M[(size_t)j * ld + col] * sg;  // L[col][j] sg_j (upper copy)
-          for (int i = col + lane; i < N; i += 64)
-            M[(size_t)i * ld + col] = fmaf(-M[(size_t)i * ld + j], lc, M[(size_t)i * ld + col]);
+          const float lc = pb[cc * pld + jj] * sg;  // L[k0+cc][j] sg_j
+          for (int i = k0 + cc + lane; i < N; i += 64) {
+            lf *row = pb + (i - k0) * pld;
+            row[cc] = fmaf(-row[jj], lc, row[cc]);
+          }
         }
         wave_sync();
       }
       if (fail && lane == 0) *flag = 1;
     }
     __syncthreads();
-    // trailing update of rows/cols [r0, N): M -= Lp diag(sg_p) Lp'
+    if constexpr (!kLds) {
+      // write the factored panel back: lower part and the L' copy
+      for (int e = tid; e < (N - k0) * kNB; e += T) {
+        const int r = e / kNB, c = e % kNB;
+        const int i = k0 + r, col = k0 + c;
+        if (c < kb && col <= i) {
+          M[(size_t)i * ld + col] = pan[e];
+          if (col < i) M[(size_t)col * ld + i] = pan[e];
+        }
+      }
+    }
+    // trailing update of rows/cols [r0, N): M -= Lp diag(sg_p) Lp', panel
+    // values read from LDS
     const int r0 = k0 + kb, R = N - r0;
     if (R > 0) {
       const int nt = (R + 3) >> 2;
@@ -304,8 +339,8 @@ __device__ __noinline__ bool signed_cholesky(MF *M, int ld, int N, int npos, li 
 #pragma unroll
           for (int a = 0; a < 4; ++a) {
             const int ia = min(i0 + a, N - 1), ja = min(j0 + a, N - 1);
-            av[a] = *reinterpret_cast<V4 *>(M + (size_t)ia * ld + k0 + c);
-            bv[a] = *reinterpret_cast<V4 *>(M + (size_t)ja * ld + k0 + c);
+            av[a] = *reinterpret_cast<const lf4 *>(pb + (ia - k0) * pld + c);
+            bv[a] = *reinterpret_cast<const lf4 *>(pb + (ja - k0) * pld + c);
           }
           const float s0 = (k0 + c + 0) < npos ? 1.f : -1.f;
           const float s1 = (k0 + c + 1) < npos ? 1.f : -1.f;
@@ -403,6 +438,46 @@ QPD void signed_solve_wave(const MF *M, int ld, int N, int npos, const lf *dinv,
   }
 }
 
+// FP64-accumulated y[i] = sum_j R[i*ld + j] x[j] (16 lanes per row).
+template <int T, class RF>
+QPD void rowdot_d(const RF *R, int ld, int rows, int cols, const lf *x, ldd *out) {
+  const int sub = threadIdx.x & 15, grp = threadIdx.x >> 4;
+  for (int i0 = 0; i0 < rows; i0 += T / 16) {
+    const int i = i0 + grp;
+    double acc = 0.0;
+    if (i < rows) {
+      const RF *Ri = R + (size_t)i * ld;
+      for (int j = sub; j < cols; j += 16) acc = fma((double)Ri[j], (double)x[j], acc);
+    }
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 16);
+    if (sub == 0 && i < rows) out[i] = acc;
+  }
+}
+
+// FP64-accumulated out[j] (+)= sum_i R[i*ld + j] x[i]; barriers inside.
+template <int T, class RF, class XF>
+QPD void coldot_d(const RF *R, int ld, int rows, int cols, const XF *x, ldd *out, bool add,
+                  ldd *part) {
+  const int cw = cols <= 64 ? 64 : (cols <= 128 ? (T >= 128 ? 128 : 64) : (T >= 256 ? 256 : T));
+  const int groups = T / cw;
+  const int g = threadIdx.x / cw, jl = threadIdx.x % cw;
+  for (int jb = 0; jb < cols; jb += cw) {
+    const int j = jb + jl;
+    double acc = 0.0;
+    if (j < cols)
+      for (int i = g; i < rows; i += groups) acc = fma((double)R[(size_t)i * ld + j], (double)x[i], acc);
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    if (g == 0 && j < cols) {
+      double s = 0.0;
+      for (int gg = 0; gg < groups; ++gg) s += part[gg * cw + jl];
+      out[j] = add ? out[j] + s : s;
+    }
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------------------
 // The per-QP context: LDS views plus this QP's global problem data.
 template <class MF>
@@ -420,6 +495,8 @@ struct Ctx {
   lf *tQ, *tGz, *tAy;
   lf *t0, *t1, *u0, *u1, *dv0, *dv1, *dinv;
   lf *part, *red;
+  lf *w0, *w1, *rr, *pan;
+  ldd *dd;
   li *role, *bidx, *elist, *iflag;
 };
 
@@ -437,6 +514,8 @@ QPD void init_ctx(Ctx<MF> &C, lf *sm, const Layout &L, MF *Mptr) {
   C.t0 = sm + L.t0; C.t1 = sm + L.t1; C.u0 = sm + L.u0; C.u1 = sm + L.u1;
   C.dv0 = sm + L.dv0; C.dv1 = sm + L.dv1; C.dinv = sm + L.dinv;
   C.part = sm + L.part; C.red = sm + L.red;
+  C.w0 = sm + L.w0; C.w1 = sm + L.w1; C.rr = sm + L.rr; C.pan = sm + L.pan;
+  C.dd = reinterpret_cast<ldd *>(sm + L.dd);
   C.role = reinterpret_cast<li *>(sm + L.role);
   C.bidx = reinterpret_cast<li *>(sm + L.bidx);
   C.elist = reinterpret_cast<li *>(sm + L.elist);
@@ -449,50 +528,39 @@ QPD void init_ctx(Ctx<MF> &C, lf *sm, const Layout &L, MF *Mptr) {
 template <int T, class CT>
 __device__ __noinline__ float residuals(CT &C, bool bounded, float kappa, float kr, bool *bad) {
   const int n = C.n, m = C.m, p = C.p, tid = threadIdx.x;
-  {
-    const lf *xv[1] = {C.x};
-    lf *o1[1] = {C.t0};
-    if (m) rowdot<T, 1>(C.G, n, m, n, xv, o1);
-    lf *o2[1] = {C.re};
-    if (p) rowdot<T, 1>(C.A, n, p, n, xv, o2);
-  }
-  {
-    const lf *xv[1] = {C.x};
-    lf *o[1] = {C.tQ};
-    coldot<T, 1>(C.Q, n, n, n, xv, o, C.part);
-    if (m) {
-      const lf *zv[1] = {C.z};
-      lf *o2[1] = {C.tGz};
-      coldot<T, 1>(C.G, n, m, n, zv, o2, C.part);
-    }
-    if (p) {
-      const lf *yv[1] = {C.y};
-      lf *o3[1] = {C.tAy};
-      coldot<T, 1>(C.A, n, p, n, yv, o3, C.part);
-    }
-  }
+  // matrix-vector products accumulated in FP64 (the FP32 iterate is exact
+  // in FP64, so the residual is limited only by the iterate's rounding)
+  ldd *gxd = C.dd, *axd = C.dd + m, *qxd = C.dd + m + p, *gzd = qxd + n, *ayd = gzd + n;
+  ldd *pd = reinterpret_cast<ldd *>(C.part);
+  if (m) rowdot_d<T>(C.G, n, m, n, C.x, gxd);
+  if (p) rowdot_d<T>(C.A, n, p, n, C.x, axd);
+  coldot_d<T>(C.Q, n, n, n, C.x, qxd, false, pd);
+  if (m) coldot_d<T>(C.G, n, m, n, C.z, gzd, false, pd);
+  if (p) coldot_d<T>(C.A, n, p, n, C.y, ayd, false, pd);
   // max-norm accumulators
   enum { RT, QX, QQ, GZ, AY, RI, GX, SS, HH, RE, AX, BB, RZS, ZZ, CC, NF, NK };
   float mx[NK];
 #pragma unroll
   for (int k = 0; k < NK; ++k) mx[k] = 0.f;
   for (int i = tid; i < n; i += T) {
-    const float gz = m ? C.tGz[i] : 0.f, ay = p ? C.tAy[i] : 0.f;
-    const float r = C.tQ[i] + C.q[i] + gz + ay;
+    const double gz = m ? gzd[i] : 0.0, ay = p ? ayd[i] : 0.0;
+    const double rd = qxd[i] + (double)C.q[i] + gz + ay;
+    const float r = (float)rd;
     C.rt[i] = r;
     mx[RT] = fmaxf(mx[RT], fabsf(r));
-    mx[QX] = fmaxf(mx[QX], fabsf(C.tQ[i]));
+    mx[QX] = fmaxf(mx[QX], fabsf((float)qxd[i]));
     mx[QQ] = fmaxf(mx[QQ], fabsf(C.q[i]));
-    mx[GZ] = fmaxf(mx[GZ], fabsf(gz));
-    mx[AY] = fmaxf(mx[AY], fabsf(ay));
+    mx[GZ] = fmaxf(mx[GZ], fabsf((float)gz));
+    mx[AY] = fmaxf(mx[AY], fabsf((float)ay));
     if (!finitef(r)) mx[NF] = 1.f;
   }
   for (int i = tid; i < m; i += T) {
-    const float gx = C.t0[i], si = C.s[i], zi = C.z[i];
-    const float r = gx + si - C.h[i];
+    const double gx = gxd[i];
+    const float si = C.s[i], zi = C.z[i];
+    const float r = (float)(gx + (double)si - (double)C.h[i]);
     C.ri[i] = r;
     mx[RI] = fmaxf(mx[RI], fabsf(r));
-    mx[GX] = fmaxf(mx[GX], fabsf(gx));
+    mx[GX] = fmaxf(mx[GX], fabsf((float)gx));
     mx[SS] = fmaxf(mx[SS], fabsf(si));
     mx[HH] = fmaxf(mx[HH], fabsf(C.h[i]));
     mx[ZZ] = fmaxf(mx[ZZ], fabsf(zi));
@@ -510,11 +578,11 @@ __device__ __noinline__ float residuals(CT &C, bool bounded, float kappa, float 
     if (!finitef(r) || !finitef(zs) || !finitef(rz) || !finitef(rs)) mx[NF] = 1.f;
   }
   for (int i = tid; i < p; i += T) {
-    const float ax = C.re[i];
-    const float r = ax - C.b[i];
+    const double ax = axd[i];
+    const float r = (float)(ax - (double)C.b[i]);
     C.re[i] = r;
     mx[RE] = fmaxf(mx[RE], fabsf(r));
-    mx[AX] = fmaxf(mx[AX], fabsf(ax));
+    mx[AX] = fmaxf(mx[AX], fabsf((float)ax));
     mx[BB] = fmaxf(mx[BB], fabsf(C.b[i]));
     if (!finitef(r)) mx[NF] = 1.f;
   }
@@ -712,6 +780,92 @@ __device__ __noinline__ void solve2(CT &C, int N, bool both) {
   __syncthreads();
 }
 
+
+// Iterative refinement of a solution u of the augmented system
+//   [[H, C'], [C, -Dl]] u = w,  H = Q + G_I' diag(wts_I) G_I,  C = [G_B; A],
+// wts = E/D (bounded form) or E (standard form / initialisation, where E
+// holds z/s or 1),
+// Dl = D/E on bounded border rows and 0 on equality rows, against the
+// operator WITHOUT any regularisation, with the residual w - K u
+// accumulated in FP64 from the original Q, G, A.  Each step solves for the
+// correction with the existing factor (one wave) and adds it.
+template <int T, int RPL, class CT>
+__device__ __noinline__ void refine(CT &C, int nb, bool bounded, const lf *w, lf *u, int steps) {
+  const int n = C.n, m = C.m, p = C.p, tid = threadIdx.x, N = n + nb + p;
+  ldd *gx = C.dd, *ax = C.dd + m, *phi = C.dd + m + p, *kx = C.dd + 2 * m + p;
+  ldd *pd = reinterpret_cast<ldd *>(C.part);
+  lf *r = C.rr;
+  for (int it = 0; it < steps; ++it) {
+    if (m) rowdot_d<T>(C.G, n, m, n, u, gx);
+    if (p) rowdot_d<T>(C.A, n, p, n, u, ax);
+    __syncthreads();
+    for (int i = tid; i < m; i += T) {
+      const int k = C.role[i];
+      const double wi = bounded ? (double)C.E[i] / (double)C.D[i] : (double)C.E[i];
+      phi[i] = k >= 0 ? (double)u[n + k] : wi * gx[i];
+    }
+    __syncthreads();
+    coldot_d<T>(C.Q, n, n, n, u, kx, false, pd);
+    if (m) coldot_d<T>(C.G, n, m, n, phi, kx, true, pd);
+    if (p) coldot_d<T>(C.A, n, p, n, u + n + nb, kx, true, pd);
+    for (int j = tid; j < n; j += T) r[j] = (float)((double)w[j] - kx[j]);
+    for (int k = tid; k < nb; k += T) {
+      const int i = C.bidx[k];
+      const double dl = bounded ? (double)C.D[i] / (double)C.E[i] : 0.0;
+      r[n + k] = (float)((double)w[n + k] - (gx[i] - dl * (double)u[n + k]));
+    }
+    for (int a = tid; a < p; a += T) r[n + nb + a] = (float)((double)w[n + nb + a] - ax[a]);
+    __syncthreads();
+    if (threadIdx.x < 64) signed_solve_wave<RPL>(C.M, C.ld, N, n, C.dinv, r);
+    __syncthreads();
+    for (int j = tid; j < N; j += T) u[j] += r[j];
+    __syncthreads();
+  }
+}
+
+
+// Add -delta to the diagonal of the border block, with delta = rel * (largest
+// squared border-row norm) / (largest diagonal of H): a Tikhonov floor on the
+// Schur complement Dl + C H^-1 C' scaled like its entries.
+template <int T, class CT>
+__device__ __noinline__ void border_delta(CT &C, int nb, float rel) {
+  const int n = C.n, K = nb + C.p, tid = threadIdx.x, ld = C.ld;
+  float mx[2] = {0.f, 0.f};
+  for (int j = tid; j < n; j += T) mx[0] = fmaxf(mx[0], C.M[(size_t)j * ld + j]);
+  for (int k = tid; k < K; k += T) {
+    float ss = 0.f;
+    for (int j = 0; j < n; ++j) {
+      const float c = C.M[(size_t)(n + k) * ld + j];
+      ss = fmaf(c, c, ss);
+    }
+    mx[1] = fmaxf(mx[1], ss);
+  }
+  block_reduce<T, OpMax, 2>(mx, C.red);
+  const float delta = fmaxf(rel * mx[1] / fmaxf(mx[0], 1e-30f), 1e-30f);
+  for (int k = tid; k < K; k += T) C.M[(size_t)(n + k) * ld + n + k] -= delta;
+  __syncthreads();
+}
+
+// Assemble and factor the bounded-form matrix.  On a pivot breakdown the
+// matrix is rebuilt with a border floor (relative 1e-6 at least) and
+// factored again; *regularised tells the caller to refine against the
+// unregularised operator.
+template <int T, class CT>
+QPD bool factor_bounded(CT &C, int nb, int ne, const lf *wts, float delta_rel, bool *regularised) {
+  const int N = C.n + nb + C.p;
+  assemble<T>(C, nb, ne, wts, true, 0.f);
+  if (delta_rel > 0.f) border_delta<T>(C, nb, delta_rel);
+  bool ok = signed_cholesky<T>(C.M, C.ld, N, C.n, C.iflag, C.pan);
+  *regularised = delta_rel > 0.f;
+  if (!ok) {
+    assemble<T>(C, nb, ne, wts, true, 0.f);
+    border_delta<T>(C, nb, fmaxf(delta_rel, 1e-6f));
+    ok = signed_cholesky<T>(C.M, C.ld, N, C.n, C.iflag, C.pan);
+    *regularised = true;
+  }
+  return ok;
+}
+
 // Bounded-form right-hand sides of the augmented system for two columns:
 //   column 0: rho = (r_t - G'(r_i + r_z - r_s), r_i - r_s - c (kappa - kt0), r_e)
 //   column 1: rho = (0, c, 0)   (derivative with respect to kappa_target)
@@ -832,17 +986,19 @@ __device__ __noinline__ bool initialize(CT &C, double &work) {
   const int ne = compact_rows<T>(C.role, m, C.elist, C.red);
   assemble<T>(C, 0, ne, C.E, false, 0.f);
   const int N = n + p;
-  const bool ok = signed_cholesky<T>(C.M, C.ld, N, n, C.iflag);
+  const bool ok = signed_cholesky<T>(C.M, C.ld, N, n, C.iflag, C.pan);
   make_dinv<T>(C, N);
   if (m) {
     const lf *hv[1] = {C.h};
     lf *o[1] = {C.tGz};
     coldot<T, 1>(C.G, n, m, n, hv, o, C.part);
   }
-  for (int i = tid; i < n; i += T) C.u0[i] = -C.q[i] + (m ? C.tGz[i] : 0.f);
-  for (int k = tid; k < p; k += T) C.u0[n + k] = C.b[k];
+  for (int i = tid; i < n; i += T) C.u0[i] = C.w0[i] = -C.q[i] + (m ? C.tGz[i] : 0.f);
+  for (int k = tid; k < p; k += T) C.u0[n + k] = C.w0[n + k] = C.b[k];
+  for (int i = tid; i < m; i += T) C.role[i] = -1;
   __syncthreads();
   solve2<T, RPL>(C, N, false);
+  refine<T, RPL>(C, 0, false, C.w0, C.u0, 2);
   for (int i = tid; i < n; i += T) C.x[i] = C.u0[i];
   for (int k = tid; k < p; k += T) C.y[k] = C.u0[n + k];
   __syncthreads();
@@ -868,6 +1024,7 @@ __device__ __noinline__ bool initialize(CT &C, double &work) {
   __syncthreads();
   const double dn = n, dm = m, dN = N;
   work += dm * dn * (dn + 1.0) + dN * dN * dN / 3.0 + 2.0 * dN * dN + 4.0 * dm * dn;
+  work += 2.0 * (2.0 * dN * dN + 2.0 * dn * dn + 8.0 * dm * dn);  // two refinement steps
   return ok;
 }
 
@@ -877,7 +1034,7 @@ __device__ __noinline__ bool initialize(CT &C, double &work) {
 // *stage on failure.  Updates x, y, v, kappa, z, s.
 template <int T, int RPL, class CT>
 __device__ __noinline__ int newton_bounded(CT &C, float &kappa, int kt_mode, float sigma, float kr,
-                       float delta_reg, double &work, int *stage) {
+                       float delta_reg, int refine_steps, double &work, int *stage) {
   const int n = C.n, m = C.m, p = C.p, tid = threadIdx.x;
   const int nb = partition_bounded<T>(C, kappa);
   const int ne = C.iflag[1];
@@ -885,8 +1042,8 @@ __device__ __noinline__ int newton_bounded(CT &C, float &kappa, int kt_mode, flo
   for (int i = tid; i < m; i += T) C.t1[i] = C.E[i] / C.D[i];
   __syncthreads();
   const int N = n + nb + p;
-  assemble<T>(C, nb, ne, C.t1, true, delta_reg);
-  const bool ok = signed_cholesky<T>(C.M, C.ld, N, n, C.iflag);
+  bool reg = false;
+  const bool ok = factor_bounded<T>(C, nb, ne, C.t1, delta_reg, &reg);
   const double dn = n, dm = m, dp = p, dN = N;
   work += 2.0 * dn * dn + 4.0 * dm * dn + 4.0 * dp * dn;            // residuals
   work += (double)ne * dn * (dn + 1.0) + dN * dN * dN / 3.0;        // assembly + factor
@@ -894,7 +1051,17 @@ __device__ __noinline__ int newton_bounded(CT &C, float &kappa, int kt_mode, flo
   if (!ok) { *stage = SG_PRED; return ST_FACT; }
   make_dinv<T>(C, N);
   rhs_bounded<T>(C, nb, kappa, nullptr, nullptr, nullptr, false);
+  const int nref = reg ? max(refine_steps, 2) : refine_steps;
+  if (nref) {
+    for (int j = tid; j < N; j += T) { C.w0[j] = C.u0[j]; C.w1[j] = C.u1[j]; }
+    __syncthreads();
+  }
   solve2<T, RPL>(C, N, true);
+  if (nref) {
+    refine<T, RPL>(C, nb, true, C.w0, C.u0, nref);
+    refine<T, RPL>(C, nb, true, C.w1, C.u1, nref);
+    work += 2.0 * nref * (2.0 * dN * dN + 4.0 * dm * dn + 2.0 * dn * dn + 4.0 * dp * dn);
+  }
   recover_bounded<T>(C, nb, true);
   // predictor step length (kappa_target = 0) and kappa_aff
   float kt;
@@ -978,7 +1145,7 @@ __device__ __noinline__ int newton_standard(CT &C, float mu, int kt_mode, float 
   __syncthreads();
   const int N = n + p;
   assemble<T>(C, 0, ne, C.E, false, delta_reg);
-  const bool ok = signed_cholesky<T>(C.M, C.ld, N, n, C.iflag);
+  const bool ok = signed_cholesky<T>(C.M, C.ld, N, n, C.iflag, C.pan);
   const double dn = n, dm = m, dp = p, dN = N;
   work += 2.0 * dn * dn + 4.0 * dm * dn + 4.0 * dp * dn;
   work += dm * dn * (dn + 1.0) + dN * dN * dN / 3.0;
@@ -1069,7 +1236,8 @@ __device__ __noinline__ int newton_standard(CT &C, float mu, int kt_mode, float 
 // Returns the final status; iters counts Newton steps taken.
 template <int T, int RPL, class CT>
 QPD int newton_loop(CT &C, bool bounded, int max_iter, float tol, int kt_mode, float sigma,
-                    float kr, float delta_reg, double &work, int &iters, float &res) {
+                    float kr, float delta_reg, int refine_steps, double &work, int &iters,
+                    float &res) {
   const int m = C.m, tid = threadIdx.x;
   int status = ST_MAXIT;
   int stage = SG_NONE;
@@ -1093,7 +1261,8 @@ QPD int newton_loop(CT &C, bool bounded, int max_iter, float tol, int kt_mode, f
     if (res < tol) { status = ST_CONV; iters = it; break; }
     if (it >= max_iter || m == 0) { status = ST_MAXIT; iters = it; break; }
     int st;
-    if (bounded) st = newton_bounded<T, RPL>(C, kappa, kt_mode, sigma, kr, delta_reg, work, &stage);
+    if (bounded)
+      st = newton_bounded<T, RPL>(C, kappa, kt_mode, sigma, kr, delta_reg, refine_steps, work, &stage);
     else st = newton_standard<T, RPL>(C, kappa, kt_mode, kr, delta_reg, work, &stage);
     if (st != ST_CONV) { status = st; iters = it + 1; break; }
   }
@@ -1114,7 +1283,7 @@ QPD void load_vectors(CT &C) {
 // the upstream gradient; returns dx in u0[0:n], dy in u0[n+nb:], dz in dv0.
 template <int T, int RPL, class CT>
 __device__ __noinline__ bool adjoint(CT &C, bool bounded, const gf *gx, const gf *gy, const gf *gz,
-                 float delta_reg, double &work) {
+                 float delta_reg, int refine_steps, double &work) {
   const int n = C.n, m = C.m, p = C.p, tid = threadIdx.x;
   float sm[1] = {0.f};
   for (int i = tid; i < m; i += T) {
@@ -1143,15 +1312,25 @@ __device__ __noinline__ bool adjoint(CT &C, bool bounded, const gf *gx, const gf
     for (int i = tid; i < m; i += T) C.E[i] = C.t1[i];
   __syncthreads();
   const int N = n + nb + p;
-  assemble<T>(C, nb, ne, C.t1, bounded, delta_reg);
-  const bool ok = signed_cholesky<T>(C.M, C.ld, N, n, C.iflag);
+  bool ok, reg = false;
+  if (bounded) {
+    ok = factor_bounded<T>(C, nb, ne, C.t1, delta_reg, &reg);
+  } else {
+    assemble<T>(C, nb, ne, C.t1, false, 0.f);
+    ok = signed_cholesky<T>(C.M, C.ld, N, n, C.iflag, C.pan);
+  }
+  const int nref = refine_steps + 2;
   const double dn = n, dN = N;
   work += (double)ne * dn * (dn + 1.0) + dN * dN * dN / 3.0 + 2.0 * dN * dN + 8.0 * m * dn;
+  work += nref * (2.0 * dN * dN + 2.0 * dn * dn + 8.0 * m * dn + 4.0 * p * dn);
   if (!ok) return false;
   make_dinv<T>(C, N);
   if (bounded) {
     rhs_bounded<T>(C, nb, kappa, gx, gz, gy, true);
+    for (int j = tid; j < N; j += T) C.w0[j] = C.u0[j];
+    __syncthreads();
     solve2<T, RPL>(C, N, false);
+    refine<T, RPL>(C, nb, true, C.w0, C.u0, nref);
     recover_bounded<T>(C, nb, false);
     // dz = E (dv + gz)
     for (int i = tid; i < m; i += T) C.dv0[i] = C.E[i] * (C.dv0[i] + (gz ? gz[i] : 0.f));
@@ -1164,10 +1343,11 @@ __device__ __noinline__ bool adjoint(CT &C, bool bounded, const gf *gx, const gf
       lf *o[1] = {C.tGz};
       coldot<T, 1>(C.G, n, m, n, xv, o, C.part);
     }
-    for (int i = tid; i < n; i += T) C.u0[i] = -gx[i] - (m ? C.tGz[i] : 0.f);
-    for (int k = tid; k < p; k += T) C.u0[n + k] = gy ? -gy[k] : 0.f;
+    for (int i = tid; i < n; i += T) C.u0[i] = C.w0[i] = -gx[i] - (m ? C.tGz[i] : 0.f);
+    for (int k = tid; k < p; k += T) C.u0[n + k] = C.w0[n + k] = gy ? -gy[k] : 0.f;
     __syncthreads();
     solve2<T, RPL>(C, N, false);
+    refine<T, RPL>(C, 0, false, C.w0, C.u0, nref);
     if (m) {
       const lf *xv[1] = {C.u0};
       lf *o[1] = {C.t0};
@@ -1239,8 +1419,8 @@ __device__ __noinline__ void write_grads(CT &C, const Params &P, size_t qi) {
 }
 
 // ---------------------------------------------------------------------------
-template <int T, int RPL, bool MLDS>
-__global__ void __launch_bounds__(T, (T >= 256 ? 2 : 4)) qp_kernel(Params P) {
+template <int T, int RPL, bool MLDS, int MODE>
+QPD void qp_body(const Params &P) {
   extern __shared__ __attribute__((aligned(16))) float smem[];
   typedef typename std::conditional<MLDS, lf, gf>::type MF;
   const int n = P.n, m = P.m, p = P.p;
@@ -1265,14 +1445,14 @@ __global__ void __launch_bounds__(T, (T >= 256 ? 2 : 4)) qp_kernel(Params P) {
   int iters = 0;
   float res = 0.f;
   int status;
-  if (P.mode == kSolve) {
+  if constexpr (MODE == kSolve) {
     const bool ok = initialize<T, RPL>(C, work);
     if (!ok) {
       status = mkstatus(ST_FACT, SG_PRED);
       res = __int_as_float(0x7fc00000);
     } else {
       status = newton_loop<T, RPL>(C, bounded, P.max_iter, P.tol, P.pc ? 0 : 1, P.sigma, 0.f,
-                                   P.delta_reg, work, iters, res);
+                                   P.delta_reg, P.refine, work, iters, res);
     }
     gf *xo = (gf *)P.x + qi * (size_t)n;
     for (int i = tid; i < n; i += T) xo[i] = C.x[i];
@@ -1297,11 +1477,11 @@ __global__ void __launch_bounds__(T, (T >= 256 ? 2 : 4)) qp_kernel(Params P) {
     }
     __syncthreads();
     status = newton_loop<T, RPL>(C, bounded, P.relax_max_iter, P.relax_tol, 2, 0.f, P.kappa_relax,
-                                 P.delta_reg, work, iters, res);
+                                 P.delta_reg, P.refine, work, iters, res);
     const gf *gx = (const gf *)P.gx + qi * (size_t)n;
     const gf *gy = P.gy ? (const gf *)P.gy + qi * (size_t)p : nullptr;
     const gf *gz = P.gz ? (const gf *)P.gz + qi * (size_t)m : nullptr;
-    const bool ok = adjoint<T, RPL>(C, bounded, gx, gy, gz, P.delta_reg, work);
+    const bool ok = adjoint<T, RPL>(C, bounded, gx, gy, gz, P.delta_reg, P.refine, work);
     if (!ok) status = mkstatus(ST_FACT, SG_BWD);
     __syncthreads();
     write_grads<T>(C, P, qi);
@@ -1317,22 +1497,37 @@ __global__ void __launch_bounds__(T, (T >= 256 ? 2 : 4)) qp_kernel(Params P) {
   }
 }
 
+// One workgroup per QP: Algorithm 1 (or the standard IPM) end to end.
+template <int T, int RPL, bool MLDS>
+__global__ void __launch_bounds__(T, (T >= 256 ? 2 : 4)) qp_solve_kernel(Params P) {
+  qp_body<T, RPL, MLDS, kSolve>(P);
+}
+
+// One workgroup per QP: relax (Algorithm 2), adjoint solve and parameter
+// gradients (Algorithm 3).
+template <int T, int RPL, bool MLDS>
+__global__ void __launch_bounds__(T, (T >= 256 ? 2 : 4)) qp_backward_kernel(Params P) {
+  qp_body<T, RPL, MLDS, kBackward>(P);
+}
+
+template <class K>
+hipError_t launch_k(K k, const Params &P, int T, size_t lds, int grid, hipStream_t st) {
+  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(T), lds, st, P);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 template <int T, int RPL>
 hipError_t launch_t(const Params &P, bool m_in_lds, size_t lds, int grid, hipStream_t st) {
-  if (m_in_lds) {
-    auto k = qp_kernel<T, RPL, true>;
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k, dim3(grid), dim3(T), lds, st, P);
-  } else {
-    auto k = qp_kernel<T, RPL, false>;
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k, dim3(grid), dim3(T), lds, st, P);
+  if (P.mode == kSolve) {
+    if (m_in_lds) return launch_k(qp_solve_kernel<T, RPL, true>, P, T, lds, grid, st);
+    return launch_k(qp_solve_kernel<T, RPL, false>, P, T, lds, grid, st);
   }
-  return hipGetLastError();
+  if (m_in_lds) return launch_k(qp_backward_kernel<T, RPL, true>, P, T, lds, grid, st);
+  return launch_k(qp_backward_kernel<T, RPL, false>, P, T, lds, grid, st);
 }
 
 }  // namespace qpk
