@@ -60,6 +60,61 @@ def cpu_baseline(P, budget_s=15.0):
                       f"{cores} worker processes with 1 BLAS thread each ({wall:.1f} s wall)"}
 
 
+def serving_bench(n_requests=1200, seed=7, rates=(0.5, 0.9), max_slots=512, iters_per_step=4):
+    """Serving workload: a stream of single QPs with n ~ U{8..256}, m = 2n,
+    p = floor(n/10) (random feasible recipe).  Saturation throughput is
+    measured closed-loop (all requests queued at once); latency
+    (completion - submission, host monotonic clock) open-loop with Poisson
+    arrivals at fractions of that rate."""
+    import paper_2605_17913_amd as qpx
+    import qpgen
+    sizes = qpgen.serving_requests(n_requests, seed)
+    probs = []
+    for (n, m, p, sd) in sizes:
+        P = qpgen.random_feasible(1, n, m, p, sd % (2**31))
+        probs.append((P.Q[0], P.q[0], P.A[0] if p else None, P.b[0] if p else None,
+                      P.G[0] if m else None, P.h[0] if m else None))
+    out = {"requests": n_requests, "n_range": [8, 256], "max_slots": max_slots,
+           "iters_per_step": iters_per_step}
+    with qpx.Server(max_slots=max_slots, iters_per_step=iters_per_step,
+                    arena_bytes=1 << 30) as srv:
+        for P in probs[:16]:  # warm-up: first launches of every kernel variant
+            srv.wait(srv.submit(*P))
+        t0 = time.perf_counter()
+        tickets = [srv.submit(*P) for P in probs]
+        res = [srv.wait(t, timeout=300) for t in tickets]
+        wall = time.perf_counter() - t0
+        mu_sat = n_requests / wall
+        out["saturation_solves_per_s"] = round(mu_sat, 1)
+        out["converged_frac"] = float(np.mean([(r["status"] & 0xff) == 0 for r in res]))
+        out["peak_resident"] = srv.stats()["peak_resident"]
+        rng = np.random.default_rng(seed)
+        for frac in rates:
+            lam = frac * mu_sat
+            arr = np.cumsum(rng.exponential(1.0 / lam, n_requests))
+            pending = {}
+            lat = []
+            t0 = time.perf_counter()
+            k = 0
+            while k < n_requests or pending:
+                now = time.perf_counter() - t0
+                while k < n_requests and arr[k] <= now:
+                    pending[srv.submit(*probs[k])] = None
+                    k += 1
+                for t in list(pending):
+                    r = srv.poll(t)
+                    if r is not None:
+                        lat.append(r["t_done"] - r["t_submit"])
+                        del pending[t]
+                if k < n_requests and not pending:
+                    time.sleep(max(0.0, min(1e-3, arr[k] - (time.perf_counter() - t0))))
+            lat = np.array(lat) * 1e3
+            out[f"rate_{frac:.2f}"] = {"offered_per_s": round(lam, 1),
+                                       "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                                       "p99_ms": round(float(np.percentile(lat, 99)), 3)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -69,6 +124,7 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ablation", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -146,6 +202,8 @@ def main():
         s2 = std["status"].cpu().numpy()
         out["standard_form"] = {"converged_frac": float(np.mean((s2 & 0xff) == 0)),
                                 "nonfinite_or_factor_fail_frac": float(np.mean((s2 & 0xff) >= 2))}
+    if not args.no_serving:
+        out["serving"] = serving_bench()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(P)
     print(json.dumps(out), flush=True)

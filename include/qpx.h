@@ -93,7 +93,7 @@ typedef struct {
                             factorisation; 0 = automatic (n)                  */
   float delta_reg;       /* relative Tikhonov floor on the bordered block (0) */
   int32_t refine_steps;  /* iterative refinement steps of each KKT solve (0)  */
-  int32_t block;         /* threads per QP: 0 = automatic, or 64/128/256/512  */
+  int32_t block;         /* threads per QP: 0 = automatic, or 128/256/512     */
 } qp_opts;
 
 typedef struct {

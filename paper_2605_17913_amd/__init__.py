@@ -23,7 +23,8 @@ import threading
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libqpx.so")
+# QPX_LIB selects another build of the same library (e.g. a profiling build)
+LIB_PATH = os.environ.get("QPX_LIB") or os.path.join(_HERE, "libqpx.so")
 
 QPX_OK, QPX_PENDING = 0, 1
 CONVERGED, MAX_ITER, NONFINITE, FACTOR_FAIL = 0, 1, 2, 3
@@ -266,3 +267,78 @@ class QPFunction(torch.autograd.Function):
 
 def qp_layer(Q, q, A, b, G, h, **options):
     return QPFunction.apply(Q, q, A, b, G, h, options)
+
+
+class Server:
+    """Continuous-batching request loop (C-ABI qp_server_*).  Requests are
+    single QPs given as host float32 arrays; results come back as numpy
+    arrays with host monotonic timestamps."""
+
+    def __init__(self, device: int = 0, max_slots: int = 256, iters_per_step: int = 4,
+                 n_max: int = 256, arena_bytes: int = 0, **solver_opts):
+        import numpy as np  # noqa: F401
+        self._np = np
+        so = make_opts(**solver_opts)
+        o = _ServerOpts(max_slots, iters_per_step, n_max, arena_bytes)
+        h = _vp()
+        _check(lib().qp_server_create(_context(device), ctypes.byref(o), ctypes.byref(so),
+                                      ctypes.byref(h)), "qp_server_create")
+        self._h = h
+        self._sizes = {}
+
+    def submit(self, Q, q, A, b, G, h) -> int:
+        np = self._np
+        f = lambda a: None if a is None else np.ascontiguousarray(a, dtype=np.float32)
+        Q, q, A, b, G, h = (f(a) for a in (Q, q, A, b, G, h))
+        n = Q.shape[0]
+        p = 0 if A is None else A.shape[0]
+        m = 0 if G is None else G.shape[0]
+        ptr = lambda a: None if a is None or a.size == 0 else a.ctypes.data_as(_vp)
+        t = ctypes.c_uint64()
+        _check(lib().qp_serve_submit(self._h, n, m, p, ptr(Q), ptr(q), ptr(A), ptr(b), ptr(G),
+                                     ptr(h), ctypes.byref(t)), "qp_serve_submit")
+        self._sizes[t.value] = (n, m, p)
+        return t.value
+
+    def poll(self, ticket: int):
+        np = self._np
+        n, m, p = self._sizes[ticket]
+        x, y = np.empty(n, np.float32), np.empty(p, np.float32)
+        z, s = np.empty(m, np.float32), np.empty(m, np.float32)
+        tm = _Timing()
+        ptr = lambda a: None if a.size == 0 else a.ctypes.data_as(_vp)
+        rc = lib().qp_serve_poll(self._h, ticket, ptr(x), ptr(y), ptr(z), ptr(s), ctypes.byref(tm))
+        if rc == QPX_PENDING:
+            return None
+        _check(rc, "qp_serve_poll")
+        del self._sizes[ticket]
+        return dict(x=x, y=y, z=z, s=s, status=tm.status, iters=tm.iters,
+                    t_submit=tm.t_submit, t_admit=tm.t_admit, t_done=tm.t_done)
+
+    def wait(self, ticket: int, timeout: float = 60.0, sleep: float = 2e-4):
+        import time
+        t0 = time.monotonic()
+        while True:
+            r = self.poll(ticket)
+            if r is not None:
+                return r
+            if time.monotonic() - t0 > timeout:
+                raise QPError(f"request {ticket} not done after {timeout} s")
+            time.sleep(sleep)
+
+    def stats(self):
+        a, c, pk = ctypes.c_uint64(), ctypes.c_uint64(), _c_int32()
+        _check(lib().qp_serve_stats(self._h, ctypes.byref(a), ctypes.byref(c), ctypes.byref(pk)),
+               "qp_serve_stats")
+        return dict(admitted=a.value, completed=c.value, peak_resident=pk.value)
+
+    def close(self):
+        if self._h is not None:
+            lib().qp_server_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -13,13 +13,6 @@
 #include "../../include/qpx.h"
 #include "qp_internal.h"
 
-struct qpx_ctx {
-  int device = 0;
-  float *ws = nullptr;     // global factor storage, grown on demand
-  size_t ws_bytes = 0;
-  std::mutex mu;           // guards ws growth
-};
-
 namespace {
 
 int set_device(const qpx_ctx *ctx) {
@@ -44,45 +37,6 @@ int ensure_ws(qpx_ctx *ctx, size_t bytes, hipStream_t st) {
   return QPX_OK;
 }
 
-struct Plan {
-  int kb = 0;
-  int threads = 256;
-  bool m_in_lds = true;
-  size_t lds = 0;
-  int64_t ws_stride = 0;
-};
-
-constexpr int kMaxN = 512;   // bordered system dimension supported by the kernels
-
-int make_plan(int n, int m, int p, const qp_opts &o, Plan *pl) {
-  int kb = o.kmax > 0 ? o.kmax : n;
-  kb = std::min(kb, m);
-  if (o.form == QPX_STANDARD) kb = 0;
-  if (kb < 0) kb = 0;
-  if (n + kb + p > kMaxN) kb = kMaxN - n - p;
-  if (kb < 0 || n + p > kMaxN) return QPX_ERR_UNSUPPORTED;
-  if (m > 4096) return QPX_ERR_UNSUPPORTED;
-  pl->kb = kb;
-  const int N = n + kb + p;
-  int T = o.block;
-  if (T == 0) T = N <= 64 ? 128 : (N <= 256 ? 256 : 512);
-  if (T != 64 && T != 128 && T != 256 && T != 512) return QPX_ERR_ARG;
-  pl->threads = T;
-  const size_t lim = qpk::lds_limit();
-  const size_t with_m = qpk::lds_bytes(n, m, p, kb, true);
-  if (with_m <= lim) {
-    pl->m_in_lds = true;
-    pl->lds = with_m;
-    pl->ws_stride = 0;
-  } else {
-    pl->m_in_lds = false;
-    pl->lds = qpk::lds_bytes(n, m, p, kb, false);
-    if (pl->lds > lim) return QPX_ERR_UNSUPPORTED;
-    pl->ws_stride = qpk::ws_floats(n, m, p, kb);
-  }
-  return QPX_OK;
-}
-
 int check_batch(const qp_batch *bt) {
   if (!bt) return QPX_ERR_ARG;
   if (bt->B < 0 || bt->n < 1 || bt->m < 0 || bt->p < 0 || bt->p >= bt->n) return QPX_ERR_ARG;
@@ -102,7 +56,7 @@ int check_opts(const qp_opts &o) {
   return QPX_OK;
 }
 
-void fill_common(qpk::Params &P, const qp_batch *bt, const qp_opts &o, const Plan &pl,
+void fill_common(qpk::Params &P, const qp_batch *bt, const qp_opts &o, const qpk::Plan &pl,
                  qpx_ctx *ctx) {
   std::memset(&P, 0, sizeof(P));
   P.B = bt->B; P.n = bt->n; P.m = bt->m; P.p = bt->p;
@@ -114,6 +68,45 @@ void fill_common(qpk::Params &P, const qp_batch *bt, const qp_opts &o, const Pla
   P.ws = pl.m_in_lds ? nullptr : ctx->ws;
   P.ws_stride = pl.ws_stride;
 }
+
+
+#ifdef QPK_PHASE_TIMING
+// Profiling builds only: collect the per-phase cycle counters of one launch
+// and print their sums over the batch to stderr.
+static void phase_report(const char *what, qpk::Params &P, hipStream_t st, bool before) {
+  static long long *buf = nullptr;
+  static size_t cap = 0;
+  const size_t need = (size_t)P.B * 16;
+  if (before) {
+    if (need > cap) {
+      if (buf) (void)hipFree(buf);
+      if (hipMalloc(&buf, need * sizeof(long long)) != hipSuccess) { buf = nullptr; cap = 0; return; }
+      cap = need;
+    }
+    (void)hipMemsetAsync(buf, 0, need * sizeof(long long), st);
+    P.phase = buf;
+    return;
+  }
+  if (!buf) return;
+  (void)hipStreamSynchronize(st);
+  long long *h = new long long[need];
+  (void)hipMemcpy(h, buf, need * sizeof(long long), hipMemcpyDeviceToHost);
+  static const char *names[16] = {"init", "resid", "part", "asm", "fact", "rhs", "solve",
+                                  "refine", "recover", "step", "bwd", "out", "", "", "", ""};
+  double tot[16] = {0};
+  for (size_t i = 0; i < (size_t)P.B; ++i)
+    for (int k = 0; k < 15; ++k) tot[k] += (double)h[i * 16 + k];
+  double all = 0;
+  for (int k = 0; k < 15; ++k) all += tot[k];
+  fprintf(stderr, "QPK_PHASES %s B=%d cycles/QP=%.0f", what, P.B, all / P.B);
+  for (int k = 0; k < 12; ++k) fprintf(stderr, " %s=%.1f%%", names[k], 100.0 * tot[k] / all);
+  fprintf(stderr, "\n");
+  delete[] h;
+}
+#define QPK_PHASES(what, P, st, before) phase_report(what, P, st, before)
+#else
+#define QPK_PHASES(what, P, st, before) ((void)0)
+#endif
 
 }  // namespace
 
@@ -169,8 +162,8 @@ int qp_solve(qpx_ctx *ctx, const qp_batch *bt, const qp_opts *opts, qp_out *out,
   if (!out->x || !out->status) return QPX_ERR_ARG;
   if (bt->p > 0 && !out->y) return QPX_ERR_ARG;
   if (bt->m > 0 && (!out->z || !out->s)) return QPX_ERR_ARG;
-  Plan pl;
-  if ((rc = make_plan(bt->n, bt->m, bt->p, o, &pl))) return rc;
+  qpk::Plan pl;
+  if ((rc = qpk::make_plan(bt->n, bt->m, bt->p, o, &pl))) return rc;
   if ((rc = set_device(ctx))) return rc;
   hipStream_t st = static_cast<hipStream_t>(stream);
   std::lock_guard<std::mutex> lk(ctx->mu);
@@ -182,7 +175,9 @@ int qp_solve(qpx_ctx *ctx, const qp_batch *bt, const qp_opts *opts, qp_out *out,
   P.x = out->x; P.y = out->y; P.z = out->z; P.s = out->s;
   P.status = out->status; P.iters = out->iters; P.res = out->res; P.work = out->work;
   P.mode = qpk::kSolve;
+  QPK_PHASES("solve", P, st, true);
   const hipError_t e = qpk::launch(P, pl.threads, pl.m_in_lds, pl.lds, bt->B, st);
+  QPK_PHASES("solve", P, st, false);
   return e == hipSuccess ? QPX_OK : QPX_ERR_HIP;
 }
 
@@ -200,8 +195,8 @@ int qp_backward(qpx_ctx *ctx, const qp_batch *bt, const qp_opts *opts, const qp_
   if (!dl_dx || !sol->x) return QPX_ERR_ARG;
   if (bt->p > 0 && !sol->y) return QPX_ERR_ARG;
   if (bt->m > 0 && (!sol->z || !sol->s)) return QPX_ERR_ARG;
-  Plan pl;
-  if ((rc = make_plan(bt->n, bt->m, bt->p, o, &pl))) return rc;
+  qpk::Plan pl;
+  if ((rc = qpk::make_plan(bt->n, bt->m, bt->p, o, &pl))) return rc;
   if ((rc = set_device(ctx))) return rc;
   hipStream_t st = static_cast<hipStream_t>(stream);
   std::lock_guard<std::mutex> lk(ctx->mu);
@@ -219,7 +214,9 @@ int qp_backward(qpx_ctx *ctx, const qp_batch *bt, const qp_opts *opts, const qp_
     P.rstatus = relaxed->status; P.riters = relaxed->iters; P.work = relaxed->work;
   }
   P.mode = qpk::kBackward;
+  QPK_PHASES("backward", P, st, true);
   const hipError_t e = qpk::launch(P, pl.threads, pl.m_in_lds, pl.lds, bt->B, st);
+  QPK_PHASES("backward", P, st, false);
   return e == hipSuccess ? QPX_OK : QPX_ERR_HIP;
 }
 

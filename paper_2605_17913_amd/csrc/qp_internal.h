@@ -5,6 +5,11 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <algorithm>
+#include <mutex>
+
+#include "../../include/qpx.h"
+
 namespace qpk {
 
 // Kernel modes.
@@ -39,12 +44,14 @@ struct Params {
   // serving
   const struct SlotDesc *desc;
   int32_t mode;
+  long long *phase;  // [B][16] phase cycle counters (profiling builds only)
 };
 
 // One resident serving slot.  All pointers are device pointers into the
 // server's arena; `state` holds x, y, z, s contiguously.
 struct SlotDesc {
-  int32_t n, m, p, flags;   // flags: bit0 = fresh (run the initialisation)
+  int32_t n, m, p, kb;      // sizes; kb = cap on bordered inequality rows
+  int32_t flags, pad_[3];   // flags: bit0 = fresh (run the initialisation)
   const float *Q, *q, *A, *b, *G, *h;
   float *state;             // x[n] y[p] z[m] s[m]
   float *ws;                // factor storage (global) or NULL
@@ -65,4 +72,56 @@ size_t lds_limit();
 hipError_t launch(const Params &P, int threads, bool m_in_lds, size_t lds,
                   int grid, hipStream_t stream);
 
+constexpr int kMaxN = 512;  // bordered system dimension supported by the kernels
+
+// Launch configuration of one problem size: border cap, threads per QP,
+// whether the factor fits LDS, dynamic LDS bytes, global factor floats.
+struct Plan {
+  int kb = 0;
+  int threads = 256;
+  bool m_in_lds = true;
+  size_t lds = 0;
+  int64_t ws_stride = 0;
+};
+
+inline int make_plan(int n, int m, int p, const qp_opts &o, Plan *pl) {
+  int kb = o.kmax > 0 ? o.kmax : n;
+  kb = std::min(kb, m);
+  if (o.form == QPX_STANDARD) kb = 0;
+  if (kb < 0) kb = 0;
+  if (n + kb + p > kMaxN) kb = kMaxN - n - p;
+  if (kb < 0 || n + p > kMaxN) return QPX_ERR_UNSUPPORTED;
+  if (m > 4096) return QPX_ERR_UNSUPPORTED;
+  pl->kb = kb;
+  const int N = n + kb + p;
+  int T = o.block;
+  if (T == 0) T = N <= 64 ? 128 : (N <= 256 ? 256 : 512);
+  if (T != 128 && T != 256 && T != 512) return QPX_ERR_ARG;
+  pl->threads = T;
+  const size_t lim = qpk::lds_limit();
+  const size_t with_m = qpk::lds_bytes(n, m, p, kb, true);
+  if (with_m <= lim) {
+    pl->m_in_lds = true;
+    pl->lds = with_m;
+    pl->ws_stride = 0;
+  } else {
+    pl->m_in_lds = false;
+    pl->lds = qpk::lds_bytes(n, m, p, kb, false);
+    if (pl->lds > lim) return QPX_ERR_UNSUPPORTED;
+    pl->ws_stride = qpk::ws_floats(n, m, p, kb);
+  }
+  return QPX_OK;
+}
+
+
 }  // namespace qpk
+
+// Library context (opaque in the C-ABI).
+struct qpx_ctx {
+  int device = 0;
+  float *ws = nullptr;     // global factor storage, grown on demand
+  size_t ws_bytes = 0;
+  std::mutex mu;           // guards ws growth
+};
+
+

@@ -77,6 +77,25 @@ QPD float readlane(float v, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 
+
+// Values that are the same in every lane.  Non-inlined helpers receive their
+// arguments in VGPRs (or read them from the stack), which hides uniformity
+// from the compiler; passing them through readfirstlane at entry puts loop
+// bounds and base addresses back into SGPRs and keeps branches scalar.
+QPD int rfl(int v) { return __builtin_amdgcn_readfirstlane(v); }
+QPD float rflf(float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); }
+template <class T>
+QPD T *rflp(T *p) {
+  if constexpr (sizeof(T *) == 4) {
+    return (T *)(uintptr_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(uintptr_t)p);
+  } else {
+    const uint64_t v = (uint64_t)(uintptr_t)p;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return (T *)(uintptr_t)(((uint64_t)hi << 32) | lo);
+  }
+}
+
 // Orders LDS / global accesses of one wavefront (lanes exchange data
 // through memory without a workgroup barrier).
 QPD void wave_sync() {
@@ -84,6 +103,25 @@ QPD void wave_sync() {
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
+
+// Optional per-phase cycle counters for profiling builds (-DQPK_PHASE_TIMING):
+// thread 0 accumulates clock64() deltas per phase in LDS; the kernel writes
+// them to Params::phase.  Compiled out otherwise.
+#ifdef QPK_PHASE_TIMING
+#define QPK_PT(C, k)                                    \
+  do {                                                  \
+    __syncthreads();                                    \
+    if (threadIdx.x == 0) {                             \
+      const long long _t = clock64();                   \
+      (C).pt[k] += _t - (C).pt[15];                     \
+      (C).pt[15] = _t;                                  \
+    }                                                   \
+  } while (0)
+#else
+#define QPK_PT(C, k) ((void)0)
+#endif
+enum Phase { PH_INIT, PH_RESID, PH_PART, PH_ASM, PH_FACT, PH_RHS, PH_SOLVE, PH_REFINE,
+             PH_RECOVER, PH_STEP, PH_BWD, PH_OUT, PH_N = 16 };
 
 struct OpSum { QPD static float f(float a, float b) { return a + b; } };
 struct OpMax { QPD static float f(float a, float b) { return fmaxf(a, b); } };
@@ -128,6 +166,18 @@ QPD float dbk(float v, float kappa, float r) {
 }
 
 // ---------------------------------------------------------------------------
+// Packed-blocked storage of the lower triangle of the bordered factor: row i
+// holds columns 0 .. 16*floor(i/16)+15 (its lower part rounded up to a whole
+// 16-column panel) plus 4 floats of padding, so every panel segment
+// M[i][k0 .. k0+15] with k0 <= i is a 16-byte-aligned run and consecutive
+// rows start on different LDS banks.  Element (i, j), j <= i, is at
+// moff(i) + j.
+__host__ __device__ inline int moff(int i) {
+  const int q = i >> 4, rem = i & 15;
+  return 20 * i + 16 * (8 * q * (q - 1) + q * rem);
+}
+
+// ---------------------------------------------------------------------------
 // Per-QP LDS layout (floats; ints share the float arena).  All blocks are
 // 4-float aligned.
 struct Layout {
@@ -151,7 +201,7 @@ __host__ __device__ inline Layout make_layout(int n, int m, int p, int kb, bool 
   Layout L;
   L.n = n; L.m = m; L.p = p; L.kb = kb;
   L.Nmax = n + kb + p;
-  L.ld = al4(L.Nmax);
+  L.ld = 0;  // unused: the factor uses the packed-blocked layout of moff()
   int o = 0;
   auto take = [&](int cnt) { int r = o; o += al4(cnt > 0 ? cnt : 1); return r; };
   L.x = take(n); L.y = take(p); L.z = take(m); L.s = take(m); L.v = take(m);
@@ -165,9 +215,9 @@ __host__ __device__ inline Layout make_layout(int n, int m, int p, int kb, bool 
   L.part = take(1024); L.red = take(16 * 32);
   L.w0 = take(L.Nmax); L.w1 = take(L.Nmax); L.rr = take(L.Nmax);
   L.dd = take(2 * (2 * m + p + 3 * n + 8));
-  L.pan = m_lds ? take(4) : take(L.Nmax * kNB + 16);
+  L.pan = take(4);
   L.role = take(m); L.bidx = take(m); L.elist = take(m); L.iflag = take(16);
-  if (m_lds) { L.M = o; o += L.Nmax * L.ld + 4; } else { L.M = -1; }
+  if (m_lds) { L.M = o; o += al4(moff(L.Nmax) + 16); } else { L.M = -1; }
   L.total = o;
   return L;
 }
@@ -250,74 +300,74 @@ QPD void coldot(const RF *R, int ld, int rows, int cols, const lf *const (&x)[NV
 // (M[j][i] = L[i][j]) so both triangular solves walk contiguous rows.
 // Returns false (uniformly) if a pivot sg_j * a_jj is not a positive
 // finite number.  RPL = rows per lane, >= ceil(N / 64).
-template <int T, class MF>
-__device__ __noinline__ bool signed_cholesky(MF *M, int ld, int N, int npos, li *flag, lf *pan) {
-  constexpr bool kLds = std::is_same<MF, lf>::value;
+template <int T, int RPL, class MF>
+__device__ __noinline__ bool signed_cholesky(MF *M, int N, int npos, li *flag) {
+  M = rflp(M); N = rfl(N); npos = rfl(npos); flag = rflp(flag);
+  typedef typename Vec4<MF>::type V4;
+  typedef typename Vec4<const MF>::type CV4;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   if (tid == 0) *flag = 0;
   __syncthreads();
+#pragma unroll 1
   for (int k0 = 0; k0 < N; k0 += kNB) {
     const int kb = min(kNB, N - k0);
-    // The panel (rows k0..N-1, columns k0..k0+kb-1) is factored in LDS: in
-    // place when M is in LDS, else in the staging buffer `pan` (row stride
-    // kNB).  Element (i, c) of the panel lives at pb[(i - k0) * pld + c].
-    lf *pb;
-    int pld;
-    if constexpr (kLds) {
-      pb = M + (size_t)k0 * ld + k0;
-      pld = ld;
-    } else {
-      pb = pan;
-      pld = kNB;
-      for (int e = tid; e < (N - k0) * kNB; e += T) {
-        const int r = e / kNB, c = e % kNB;
-        pan[e] = c < kb ? M[(size_t)(k0 + r) * ld + k0 + c] : 0.f;
-      }
-      __syncthreads();
-    }
     if (wid == 0) {
-      bool fail = false;
-      for (int jj = 0; jj < kb; ++jj) {
-        const int j = k0 + jj;
-        const float sg = j < npos ? 1.f : -1.f;
-        const float tt = sg * pb[jj * pld + jj];
-        const bool ok = tt > 0.f && tt <= FLT_MAX;
-        fail |= !ok;
-        const float d = ok ? sqrtf(tt) : 1.f;
-        const float inv = sg / d;
-        wave_sync();
-        if (lane == 0) pb[jj * pld + jj] = d;
-        for (int i = j + 1 + lane; i < N; i += 64) {
-          const float l = pb[(i - k0) * pld + jj] * inv;
-          pb[(i - k0) * pld + jj] = l;
-          if constexpr (kLds) M[(size_t)j * ld + i] = l;  // copy of L' in the upper triangle
+      // panel rows k0 + lane + 64 t, columns k0 .. k0+15, held in registers
+      float P[RPL][kNB];
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) {
+        const int i = k0 + lane + 64 * t;
+        const bool in = i < N;
+        const MF *row = M + moff(min(i, N - 1)) + k0;
+#pragma unroll
+        for (int c = 0; c < kNB; c += 4) {
+          const f4v v4 = *reinterpret_cast<CV4 *>(row + c);
+          P[t][c] = in ? v4.x : 0.f;
+          P[t][c + 1] = in ? v4.y : 0.f;
+          P[t][c + 2] = in ? v4.z : 0.f;
+          P[t][c + 3] = in ? v4.w : 0.f;
         }
-        wave_sync();
-        for (int cc = jj + 1; cc < kb; ++cc) {
-          const float lc = pb[cc * pld + jj] * sg;  // L[k0+cc][j] sg_j
-          for (int i = k0 + cc + lane; i < N; i += 64) {
-            lf *row = pb + (i - k0) * pld;
-            row[cc] = fmaf(-row[jj], lc, row[cc]);
+      }
+      bool fail = false;
+#pragma unroll
+      for (int jj = 0; jj < kNB; ++jj) {
+        if (jj < kb) {
+          // row k0+jj is in lane jj, slot 0
+          const float sg = (k0 + jj) < npos ? 1.f : -1.f;
+          const float tt = sg * readlane(P[0][jj], jj);
+          const bool ok = tt > 0.f && tt <= FLT_MAX;
+          fail |= !ok;
+          const float d = ok ? sqrtf(tt) : 1.f;
+          const float inv = sg / d;
+#pragma unroll
+          for (int t = 0; t < RPL; ++t) {
+            const int r = lane + 64 * t;
+            P[t][jj] = r > jj ? P[t][jj] * inv : (r == jj ? d : P[t][jj]);
+          }
+#pragma unroll
+          for (int cc = jj + 1; cc < kNB; ++cc) {
+            const float lc = readlane(P[0][jj], cc) * sg;  // L[k0+cc][k0+jj] sg
+#pragma unroll
+            for (int t = 0; t < RPL; ++t) P[t][cc] = fmaf(-P[t][jj], lc, P[t][cc]);
           }
         }
-        wave_sync();
+      }
+      // write back whole 16-column segments (entries right of the diagonal
+      // of the diagonal block land in the row's padding and are never read)
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) {
+        const int i = k0 + lane + 64 * t;
+        if (i < N) {
+          MF *row = M + moff(i) + k0;
+#pragma unroll
+          for (int c = 0; c < kNB; c += 4)
+            *reinterpret_cast<V4 *>(row + c) = f4v{P[t][c], P[t][c + 1], P[t][c + 2], P[t][c + 3]};
+        }
       }
       if (fail && lane == 0) *flag = 1;
     }
     __syncthreads();
-    if constexpr (!kLds) {
-      // write the factored panel back: lower part and the L' copy
-      for (int e = tid; e < (N - k0) * kNB; e += T) {
-        const int r = e / kNB, c = e % kNB;
-        const int i = k0 + r, col = k0 + c;
-        if (c < kb && col <= i) {
-          M[(size_t)i * ld + col] = pan[e];
-          if (col < i) M[(size_t)col * ld + i] = pan[e];
-        }
-      }
-    }
-    // trailing update of rows/cols [r0, N): M -= Lp diag(sg_p) Lp', panel
-    // values read from LDS
+    // trailing update of rows/cols [r0, N): M -= Lp diag(sg_p) Lp'
     const int r0 = k0 + kb, R = N - r0;
     if (R > 0) {
       const int nt = (R + 3) >> 2;
@@ -328,6 +378,12 @@ __device__ __noinline__ bool signed_cholesky(MF *M, int ld, int N, int npos, li 
         while (ti * (ti + 1) / 2 > t) --ti;
         const int tj = t - ti * (ti + 1) / 2;
         const int i0 = r0 + 4 * ti, j0 = r0 + 4 * tj;
+        int oi[4], oj[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          oi[a] = moff(min(i0 + a, N - 1));
+          oj[a] = moff(min(j0 + a, N - 1));
+        }
         float acc[4][4];
 #pragma unroll
         for (int a = 0; a < 4; ++a)
@@ -338,9 +394,8 @@ __device__ __noinline__ bool signed_cholesky(MF *M, int ld, int N, int npos, li 
           f4v av[4], bv[4];
 #pragma unroll
           for (int a = 0; a < 4; ++a) {
-            const int ia = min(i0 + a, N - 1), ja = min(j0 + a, N - 1);
-            av[a] = *reinterpret_cast<const lf4 *>(pb + (ia - k0) * pld + c);
-            bv[a] = *reinterpret_cast<const lf4 *>(pb + (ja - k0) * pld + c);
+            av[a] = *reinterpret_cast<CV4 *>(M + oi[a] + k0 + c);
+            bv[a] = *reinterpret_cast<CV4 *>(M + oj[a] + k0 + c);
           }
           const float s0 = (k0 + c + 0) < npos ? 1.f : -1.f;
           const float s1 = (k0 + c + 1) < npos ? 1.f : -1.f;
@@ -369,7 +424,7 @@ __device__ __noinline__ bool signed_cholesky(MF *M, int ld, int N, int npos, li 
 #pragma unroll
             for (int bq = 0; bq < 4; ++bq) {
               const int j = j0 + bq;
-              if (j <= i) M[(size_t)i * ld + j] -= acc[a][bq];
+              if (j <= i) M[oi[a] + j] -= acc[a][bq];
             }
           }
         }
@@ -385,55 +440,91 @@ __device__ __noinline__ bool signed_cholesky(MF *M, int ld, int N, int npos, li 
 // rows lane + 64 t).  Uses the L' copy in the strict upper triangle for the
 // forward sweep and L's rows for the backward sweep; dinv[j] = 1 / L[j][j].
 template <int RPL, class MF>
-QPD void signed_solve_wave(const MF *M, int ld, int N, int npos, const lf *dinv, lf *r) {
+QPD void signed_solve_wave(const MF *M, int N, int npos, const lf *dinv, lf *r) {
+  typedef typename Vec4<const MF>::type CV4;
+  static_assert(kNB % RPL == 0, "row slot must be static within a block");
   const int lane = threadIdx.x & 63;
+  // lane l owns rows RPL*l + t, so row j sits in lane j/RPL, slot j%RPL
   float a[RPL];
 #pragma unroll
   for (int t = 0; t < RPL; ++t) {
-    const int i = lane + 64 * t;
+    const int i = RPL * lane + t;
     a[t] = i < N ? r[i] : 0.f;
   }
-  // forward: L w = r
-  for (int j = 0; j < N; ++j) {
-    const int tj = j >> 6, lj = j & 63;
-    float rj = 0.f;
-#pragma unroll
-    for (int t = 0; t < RPL; ++t)
-      if (t == tj) rj = readlane(a[t], lj);
-    const float wj = rj * dinv[j];
-    const MF *Lr = M + (size_t)j * ld;  // L[i][j] = M[j][i] for i > j
+  // Forward sweep L w = r, column oriented: once w_j = a_j / L[j][j] is
+  // known every row i > j subtracts L[i][j] w_j.  Per 16-column block each
+  // lane loads its rows' segments L[i][j0..j0+15] (contiguous) with entries
+  // on and right of the diagonal zeroed; the owning lane stores w_j.
+#pragma unroll 1
+  for (int j0 = 0; j0 < N; j0 += kNB) {
+    float Lc[RPL][kNB], dv[kNB];
 #pragma unroll
     for (int t = 0; t < RPL; ++t) {
-      const int i = lane + 64 * t;
-      if (i > j && i < N) a[t] = fmaf(-Lr[i], wj, a[t]);
-      if (i == j) a[t] = wj;
+      const int i = RPL * lane + t;
+      const bool in = i >= j0 && i < N;
+      const MF *row = M + moff(in ? i : j0) + j0;
+#pragma unroll
+      for (int c = 0; c < kNB; c += 4) {
+        const f4v v4 = *reinterpret_cast<CV4 *>(row + c);
+        Lc[t][c] = v4.x; Lc[t][c + 1] = v4.y; Lc[t][c + 2] = v4.z; Lc[t][c + 3] = v4.w;
+      }
+#pragma unroll
+      for (int c = 0; c < kNB; ++c) {
+        const int col = j0 + c;
+        Lc[t][c] = (in && col < i) ? Lc[t][c] : 0.f;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < kNB; ++c) dv[c] = dinv[min(j0 + c, N - 1)];
+#pragma unroll
+    for (int c = 0; c < kNB; ++c) {
+      const int j = j0 + c;
+      if (j < N) {
+        const float wj = readlane(a[c % RPL], j / RPL) * dv[c];
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) a[t] = fmaf(-Lc[t][c], wj, a[t]);
+        if (lane == j / RPL) a[c % RPL] = wj;
+      }
     }
   }
   // sign: w <- sg w
 #pragma unroll
   for (int t = 0; t < RPL; ++t) {
-    const int i = lane + 64 * t;
+    const int i = RPL * lane + t;
     if (i >= npos) a[t] = -a[t];
   }
-  // backward: L' u = w
-  for (int j = N - 1; j >= 0; --j) {
-    const int tj = j >> 6, lj = j & 63;
-    float rj = 0.f;
+  // Backward sweep L' u = w: once u_j = a_j / L[j][j] is known every row
+  // i < j subtracts L[j][i] u_j; row j of L is read across the lanes (RPL
+  // contiguous floats per lane); the owning lane stores u_j.
+#pragma unroll 1
+  for (int b0 = ((N - 1) / kNB) * kNB; b0 >= 0; b0 -= kNB) {
+    float Lr[RPL][kNB], dv[kNB];
 #pragma unroll
-    for (int t = 0; t < RPL; ++t)
-      if (t == tj) rj = readlane(a[t], lj);
-    const float uj = rj * dinv[j];
-    const MF *Lr = M + (size_t)j * ld;  // L[j][i] for i < j
+    for (int c = 0; c < kNB; ++c) {
+      const int j = min(b0 + c, N - 1);
+      const MF *row = M + moff(j);
 #pragma unroll
-    for (int t = 0; t < RPL; ++t) {
-      const int i = lane + 64 * t;
-      if (i < j) a[t] = fmaf(-Lr[i], uj, a[t]);
-      if (i == j) a[t] = uj;
+      for (int t = 0; t < RPL; ++t) {
+        const int i = RPL * lane + t;
+        const float v = row[min(i, j)];
+        Lr[t][c] = (b0 + c < N && i < j) ? v : 0.f;
+      }
+      dv[c] = dinv[j];
+    }
+#pragma unroll
+    for (int c = kNB - 1; c >= 0; --c) {
+      const int j = b0 + c;
+      if (j < N) {
+        const float uj = readlane(a[c % RPL], j / RPL) * dv[c];
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) a[t] = fmaf(-Lr[t][c], uj, a[t]);
+        if (lane == j / RPL) a[c % RPL] = uj;
+      }
     }
   }
 #pragma unroll
   for (int t = 0; t < RPL; ++t) {
-    const int i = lane + 64 * t;
+    const int i = RPL * lane + t;
     if (i < N) r[i] = a[t];
   }
 }
@@ -498,6 +589,7 @@ struct Ctx {
   lf *w0, *w1, *rr, *pan;
   ldd *dd;
   li *role, *bidx, *elist, *iflag;
+  __attribute__((address_space(3))) long long *pt;
 };
 
 template <class MF>
@@ -522,11 +614,38 @@ QPD void init_ctx(Ctx<MF> &C, lf *sm, const Layout &L, MF *Mptr) {
   C.iflag = reinterpret_cast<li *>(sm + L.iflag);
 }
 
+
+// Uniform copy of a context (see rfl).
+template <class MF>
+QPD Ctx<MF> uctx(const Ctx<MF> &I) {
+  Ctx<MF> C;
+  C.L = I.L;
+  C.n = rfl(I.n); C.m = rfl(I.m); C.p = rfl(I.p); C.kb = rfl(I.kb); C.ld = rfl(I.ld);
+  C.Q = rflp(I.Q); C.q_g = rflp(I.q_g); C.A = rflp(I.A); C.b_g = rflp(I.b_g);
+  C.G = rflp(I.G); C.h_g = rflp(I.h_g);
+  C.sm = rflp(I.sm); C.M = rflp(I.M);
+  C.x = rflp(I.x); C.y = rflp(I.y); C.z = rflp(I.z); C.s = rflp(I.s); C.v = rflp(I.v);
+  C.q = rflp(I.q); C.h = rflp(I.h); C.b = rflp(I.b);
+  C.E = rflp(I.E); C.D = rflp(I.D); C.c = rflp(I.c);
+  C.rt = rflp(I.rt); C.ri = rflp(I.ri); C.re = rflp(I.re); C.rz = rflp(I.rz); C.rs = rflp(I.rs);
+  C.tQ = rflp(I.tQ); C.tGz = rflp(I.tGz); C.tAy = rflp(I.tAy);
+  C.t0 = rflp(I.t0); C.t1 = rflp(I.t1); C.u0 = rflp(I.u0); C.u1 = rflp(I.u1);
+  C.dv0 = rflp(I.dv0); C.dv1 = rflp(I.dv1); C.dinv = rflp(I.dinv);
+  C.part = rflp(I.part); C.red = rflp(I.red);
+  C.w0 = rflp(I.w0); C.w1 = rflp(I.w1); C.rr = rflp(I.rr); C.pan = rflp(I.pan);
+  C.dd = rflp(I.dd);
+  C.role = rflp(I.role); C.bidx = rflp(I.bidx); C.elist = rflp(I.elist); C.iflag = rflp(I.iflag);
+  C.pt = rflp(I.pt);
+  return C;
+}
+
 // Residuals at (x, y, z, s) and, for the bounded form, (v, kappa).
 // Returns the scaled residual measure (uniform); `bad` = a non-finite value
 // was seen.  complementarity: max(z s) (solve) or max|z s - kr| / kr (relax).
 template <int T, class CT>
-__device__ __noinline__ float residuals(CT &C, bool bounded, float kappa, float kr, bool *bad) {
+__device__ __noinline__ float residuals(CT &Cin_, bool bounded, float kappa, float kr, bool *bad) {
+  CT C = uctx(Cin_);
+  bounded = rfl(bounded); kappa = rflf(kappa); kr = rflf(kr);
   const int n = C.n, m = C.m, p = C.p, tid = threadIdx.x;
   // matrix-vector products accumulated in FP64 (the FP32 iterate is exact
   // in FP64, so the residual is limited only by the iterate's rounding)
@@ -629,7 +748,9 @@ QPD int compact_rows(const li *flag, int m, li *out, lf *red) {
 // number of bordered rows nb; fills E, D, c, role (border index or -1),
 // bidx (border rows), elist (eliminated rows) and iflag[1] = #eliminated.
 template <int T, class CT>
-__device__ __noinline__ int partition_bounded(CT &C, float kappa) {
+__device__ __noinline__ int partition_bounded(CT &Cin_, float kappa) {
+  CT C = uctx(Cin_);
+  kappa = rflf(kappa);
   const int m = C.m, tid = threadIdx.x;
   li *cand = C.role;  // temporarily: candidate flags
   float cnt[1] = {0.f};
@@ -683,54 +804,97 @@ __device__ __noinline__ int partition_bounded(CT &C, float kappa) {
 // z/s standard); border rows = G[bidx] then A; Dl = dl (per border row) and
 // delta on the diagonal of the border block.
 template <int T, class CT>
-__device__ __noinline__ void assemble(CT &C, int nb, int ne, const lf *wts, bool bounded, float delta) {
-  const int n = C.n, p = C.p, tid = threadIdx.x, ld = C.ld;
+__device__ __noinline__ void assemble(CT &Cin_, int nb, int ne, const lf *wts, bool bounded, float delta) {
+  CT C = uctx(Cin_);
+  nb = rfl(nb); ne = rfl(ne); wts = rflp(wts); bounded = rfl(bounded); delta = rflf(delta);
+  const int n = C.n, p = C.p, tid = threadIdx.x;
   auto *M = C.M;
-  // H block in 4x4 tiles
+  // H block in 4x4 tiles.  Rows of G_I are staged through LDS in chunks
+  // (coalesced cooperative loads), then each tile thread reads its 4 + 4
+  // entries per row as 16-byte LDS loads.  The staging area is the (not yet
+  // written) border part of M when M is in LDS, else the `part` buffer.
+  const int ldg = al4(n);
+  lf *stage = C.part;
+  int cap = 2 * T;
+  if constexpr (std::is_same<typename CT::MT, lf>::value) {
+    const int N = n + nb + p;
+    const int room = moff(N) - moff(n);
+    if (room > cap) { stage = (lf *)C.M + moff(n); cap = room; }
+  }
+  const int R = max(1, cap / ldg);
   const int nt = (n + 3) >> 2;
   const int ntiles = nt * (nt + 1) / 2;
-  for (int t = tid; t < ntiles; t += T) {
+  int i0 = 0, j0 = 0;
+  const bool tile = tid < ntiles;
+  if (tile) {
+    const int t = tid;
     int ti = (int)((sqrtf(8.f * (float)t + 1.f) - 1.f) * 0.5f);
     while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
     while (ti * (ti + 1) / 2 > t) --ti;
     const int tj = t - ti * (ti + 1) / 2;
-    const int i0 = 4 * ti, j0 = 4 * tj;
+    i0 = 4 * ti;
+    j0 = 4 * tj;
+  }
+  // ntiles <= T for n <= 4 * floor(sqrt(2T)) (n <= 88 at T = 256); larger n
+  // loop over tile groups below
+  for (int tb = 0; tb < ntiles; tb += T) {
+    const int t = tb + tid;
+    const bool act = t < ntiles;
+    if (tb > 0 && act) {
+      int ti = (int)((sqrtf(8.f * (float)t + 1.f) - 1.f) * 0.5f);
+      while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+      while (ti * (ti + 1) / 2 > t) --ti;
+      const int tj = t - ti * (ti + 1) / 2;
+      i0 = 4 * ti;
+      j0 = 4 * tj;
+    }
     float acc[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
       for (int bq = 0; bq < 4; ++bq) {
         const int i = min(i0 + a, n - 1), j = min(j0 + bq, n - 1);
-        acc[a][bq] = C.Q[(size_t)i * n + j];
+        acc[a][bq] = act ? C.Q[(size_t)i * n + j] : 0.f;
       }
+    for (int k0 = 0; k0 < ne; k0 += R) {
+      const int kr = min(R, ne - k0);
+      __syncthreads();  // the previous chunk has been consumed
+      for (int e = tid; e < kr * ldg; e += T) {
+        const int r = e / ldg, j = e - r * ldg;
+        stage[e] = j < n ? C.G[(size_t)C.elist[k0 + r] * n + j] : 0.f;
+      }
+      __syncthreads();
+      if (act) {
 #pragma unroll 2
-    for (int k = 0; k < ne; ++k) {
-      const int r = C.elist[k];
-      const float w = wts[r];
-      const gf *gr = C.G + (size_t)r * n;
-      float gi[4], gj[4];
+        for (int r = 0; r < kr; ++r) {
+          const float w = wts[C.elist[k0 + r]];
+          const f4v gi = *reinterpret_cast<const lf4 *>(stage + r * ldg + i0);
+          const f4v gj = *reinterpret_cast<const lf4 *>(stage + r * ldg + j0) * w;
+          const float gia[4] = {gi.x, gi.y, gi.z, gi.w};
+          const float gja[4] = {gj.x, gj.y, gj.z, gj.w};
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int bq = 0; bq < 4; ++bq) acc[a][bq] = fmaf(gia[a], gja[bq], acc[a][bq]);
+        }
+      }
+    }
+    __syncthreads();  // the staging area may alias M's border rows
+    if (act) {
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
-        gi[a] = gr[min(i0 + a, n - 1)];
-        gj[a] = w * gr[min(j0 + a, n - 1)];
-      }
+        const int i = i0 + a;
+        if (i < n) {
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int bq = 0; bq < 4; ++bq) acc[a][bq] = fmaf(gi[a], gj[bq], acc[a][bq]);
-    }
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const int i = i0 + a;
-      if (i < n) {
-#pragma unroll
-        for (int bq = 0; bq < 4; ++bq) {
-          const int j = j0 + bq;
-          if (j <= i) M[(size_t)i * ld + j] = acc[a][bq];
+          for (int bq = 0; bq < 4; ++bq) {
+            const int j = j0 + bq;
+            if (j <= i) M[moff(i) + j] = acc[a][bq];
+          }
         }
       }
     }
   }
+  (void)tile;
   // border rows: [C | -Dl (lower part)]
   const int K = nb + p;
   for (int e = tid; e < K * (n + K); e += T) {
@@ -753,7 +917,7 @@ __device__ __noinline__ void assemble(CT &C, int nb, int ne, const lf *wts, bool
         val = -(dl + delta);
       }
     }
-    M[(size_t)row * ld + col] = val;
+    M[moff(row) + col] = val;
   }
   __syncthreads();
 }
@@ -761,21 +925,23 @@ __device__ __noinline__ void assemble(CT &C, int nb, int ne, const lf *wts, bool
 // dinv[j] = 1 / L[j][j]
 template <int T, class CT>
 QPD void make_dinv(CT &C, int N) {
-  for (int j = threadIdx.x; j < N; j += T) C.dinv[j] = 1.f / C.M[(size_t)j * C.ld + j];
+  for (int j = threadIdx.x; j < N; j += T) C.dinv[j] = 1.f / C.M[moff(j) + j];
   __syncthreads();
 }
 
 // Solve for both right-hand sides u0 and u1 (wave 0 and wave 1 in parallel
 // when the workgroup has two waves).
 template <int T, int RPL, class CT>
-__device__ __noinline__ void solve2(CT &C, int N, bool both) {
+__device__ __noinline__ void solve2(CT &Cin_, int N, bool both) {
+  CT C = uctx(Cin_);
+  N = rfl(N); both = rfl(both);
   const int wid = threadIdx.x >> 6;
   if constexpr (T >= 128) {
-    if (wid == 0) signed_solve_wave<RPL>(C.M, C.ld, N, C.n, C.dinv, C.u0);
-    else if (wid == 1 && both) signed_solve_wave<RPL>(C.M, C.ld, N, C.n, C.dinv, C.u1);
+    if (wid == 0) signed_solve_wave<RPL>(C.M, N, C.n, C.dinv, C.u0);
+    else if (wid == 1 && both) signed_solve_wave<RPL>(C.M, N, C.n, C.dinv, C.u1);
   } else {
-    signed_solve_wave<RPL>(C.M, C.ld, N, C.n, C.dinv, C.u0);
-    if (both) signed_solve_wave<RPL>(C.M, C.ld, N, C.n, C.dinv, C.u1);
+    signed_solve_wave<RPL>(C.M, N, C.n, C.dinv, C.u0);
+    if (both) signed_solve_wave<RPL>(C.M, N, C.n, C.dinv, C.u1);
   }
   __syncthreads();
 }
@@ -790,7 +956,9 @@ __device__ __noinline__ void solve2(CT &C, int N, bool both) {
 // accumulated in FP64 from the original Q, G, A.  Each step solves for the
 // correction with the existing factor (one wave) and adds it.
 template <int T, int RPL, class CT>
-__device__ __noinline__ void refine(CT &C, int nb, bool bounded, const lf *w, lf *u, int steps) {
+__device__ __noinline__ void refine(CT &Cin_, int nb, bool bounded, const lf *w, lf *u, int steps) {
+  CT C = uctx(Cin_);
+  nb = rfl(nb); bounded = rfl(bounded); w = rflp(w); u = rflp(u); steps = rfl(steps);
   const int n = C.n, m = C.m, p = C.p, tid = threadIdx.x, N = n + nb + p;
   ldd *gx = C.dd, *ax = C.dd + m, *phi = C.dd + m + p, *kx = C.dd + 2 * m + p;
   ldd *pd = reinterpret_cast<ldd *>(C.part);
@@ -816,7 +984,7 @@ __device__ __noinline__ void refine(CT &C, int nb, bool bounded, const lf *w, lf
     }
     for (int a = tid; a < p; a += T) r[n + nb + a] = (float)((double)w[n + nb + a] - ax[a]);
     __syncthreads();
-    if (threadIdx.x < 64) signed_solve_wave<RPL>(C.M, C.ld, N, n, C.dinv, r);
+    if (threadIdx.x < 64) signed_solve_wave<RPL>(C.M, N, n, C.dinv, r);
     __syncthreads();
     for (int j = tid; j < N; j += T) u[j] += r[j];
     __syncthreads();
@@ -828,21 +996,23 @@ __device__ __noinline__ void refine(CT &C, int nb, bool bounded, const lf *w, lf
 // squared border-row norm) / (largest diagonal of H): a Tikhonov floor on the
 // Schur complement Dl + C H^-1 C' scaled like its entries.
 template <int T, class CT>
-__device__ __noinline__ void border_delta(CT &C, int nb, float rel) {
-  const int n = C.n, K = nb + C.p, tid = threadIdx.x, ld = C.ld;
+__device__ __noinline__ void border_delta(CT &Cin_, int nb, float rel) {
+  CT C = uctx(Cin_);
+  nb = rfl(nb); rel = rflf(rel);
+  const int n = C.n, K = nb + C.p, tid = threadIdx.x;
   float mx[2] = {0.f, 0.f};
-  for (int j = tid; j < n; j += T) mx[0] = fmaxf(mx[0], C.M[(size_t)j * ld + j]);
+  for (int j = tid; j < n; j += T) mx[0] = fmaxf(mx[0], C.M[moff(j) + j]);
   for (int k = tid; k < K; k += T) {
     float ss = 0.f;
     for (int j = 0; j < n; ++j) {
-      const float c = C.M[(size_t)(n + k) * ld + j];
+      const float c = C.M[moff(n + k) + j];
       ss = fmaf(c, c, ss);
     }
     mx[1] = fmaxf(mx[1], ss);
   }
   block_reduce<T, OpMax, 2>(mx, C.red);
   const float delta = fmaxf(rel * mx[1] / fmaxf(mx[0], 1e-30f), 1e-30f);
-  for (int k = tid; k < K; k += T) C.M[(size_t)(n + k) * ld + n + k] -= delta;
+  for (int k = tid; k < K; k += T) C.M[moff(n + k) + n + k] -= delta;
   __syncthreads();
 }
 
@@ -850,17 +1020,19 @@ __device__ __noinline__ void border_delta(CT &C, int nb, float rel) {
 // matrix is rebuilt with a border floor (relative 1e-6 at least) and
 // factored again; *regularised tells the caller to refine against the
 // unregularised operator.
-template <int T, class CT>
+template <int T, int RPL, class CT>
 QPD bool factor_bounded(CT &C, int nb, int ne, const lf *wts, float delta_rel, bool *regularised) {
   const int N = C.n + nb + C.p;
   assemble<T>(C, nb, ne, wts, true, 0.f);
   if (delta_rel > 0.f) border_delta<T>(C, nb, delta_rel);
-  bool ok = signed_cholesky<T>(C.M, C.ld, N, C.n, C.iflag, C.pan);
+  QPK_PT(C, PH_ASM);
+  bool ok = signed_cholesky<T, RPL>(C.M, N, C.n, C.iflag);
+  QPK_PT(C, PH_FACT);
   *regularised = delta_rel > 0.f;
   if (!ok) {
     assemble<T>(C, nb, ne, wts, true, 0.f);
     border_delta<T>(C, nb, fmaxf(delta_rel, 1e-6f));
-    ok = signed_cholesky<T>(C.M, C.ld, N, C.n, C.iflag, C.pan);
+    ok = signed_cholesky<T, RPL>(C.M, N, C.n, C.iflag);
     *regularised = true;
   }
   return ok;
@@ -874,8 +1046,11 @@ QPD bool factor_bounded(CT &C, int nb, int ne, const lf *wts, float delta_rel, b
 //   u = [ -rho1 - G' psi ;  -rho2_B ;  -rho3 ].
 // rho2 of each column is left in dv0 / dv1 for the recovery.
 template <int T, class CT>
-__device__ __noinline__ void rhs_bounded(CT &C, int nb, float kappa, const gf *gx, const gf *gz,
+__device__ __noinline__ void rhs_bounded(CT &Cin_, int nb, float kappa, const gf *gx, const gf *gz,
                      const gf *gy, bool adj) {
+  CT C = uctx(Cin_);
+  nb = rfl(nb); kappa = rflf(kappa); adj = rfl(adj);
+  gx = rflp(gx); gz = rflp(gz); gy = rflp(gy);
   const int n = C.n, m = C.m, p = C.p, tid = threadIdx.x;
   // phi0 = -(r_i + r_z - r_s) + psi0 would give u_x = -r_t - G' phi0;
   // we compute w0 = (r_i + r_z - r_s) - psi0 so u_x = -r_t + G' w0, and
@@ -936,7 +1111,9 @@ __device__ __noinline__ void rhs_bounded(CT &C, int nb, float kappa, const gf *g
 // Recover dv for the solved columns: eliminated rows dv = (G dx + rho2)/D,
 // border rows dv = du / E.  rho2 is read from dv0 / dv1 and overwritten.
 template <int T, class CT>
-__device__ __noinline__ void recover_bounded(CT &C, int nb, bool both) {
+__device__ __noinline__ void recover_bounded(CT &Cin_, int nb, bool both) {
+  CT C = uctx(Cin_);
+  nb = rfl(nb); both = rfl(both);
   const int n = C.n, m = C.m, tid = threadIdx.x;
   if (!m) return;
   if (both) {
@@ -978,7 +1155,8 @@ QPD int mkstatus(int st, int stage) { return st | (stage << 8); }
 // Initialisation (CVXOPT convention): solve [[Q+G'G, A'], [A, 0]] [x; y] =
 // [-q + G'h; b], zt = Gx - h, s = -zt, z = zt, each shifted positive.
 template <int T, int RPL, class CT>
-__device__ __noinline__ bool initialize(CT &C, double &work) {
+__device__ __noinline__ bool initialize(CT &Cin_, double &work) {
+  CT C = uctx(Cin_);
   const int n = C.n, m = C.m, p = C.p, tid = threadIdx.x;
   for (int i = tid; i < m; i += T) C.E[i] = 1.f;  // unit weights
   for (int i = tid; i < m; i += T) C.role[i] = 1;
@@ -986,7 +1164,7 @@ __device__ __noinline__ bool initialize(CT &C, double &work) {
   const int ne = compact_rows<T>(C.role, m, C.elist, C.red);
   assemble<T>(C, 0, ne, C.E, false, 0.f);
   const int N = n + p;
-  const bool ok = signed_cholesky<T>(C.M, C.ld, N, n, C.iflag, C.pan);
+  const bool ok = signed_cholesky<T, RPL>(C.M, N, n, C.iflag);
   make_dinv<T>(C, N);
   if (m) {
     const lf *hv[1] = {C.h};
@@ -1033,17 +1211,21 @@ __device__ __noinline__ bool initialize(CT &C, double &work) {
 // Returns a status code (ST_CONV meaning "keep going"), with the stage in
 // *stage on failure.  Updates x, y, v, kappa, z, s.
 template <int T, int RPL, class CT>
-__device__ __noinline__ int newton_bounded(CT &C, float &kappa, int kt_mode, float sigma, float kr,
+__device__ __noinline__ int newton_bounded(CT &Cin_, float &kappa, int kt_mode, float sigma, float kr,
                        float delta_reg, int refine_steps, double &work, int *stage) {
+  CT C = uctx(Cin_);
+  kappa = rflf(kappa); kt_mode = rfl(kt_mode); sigma = rflf(sigma); kr = rflf(kr);
+  delta_reg = rflf(delta_reg); refine_steps = rfl(refine_steps);
   const int n = C.n, m = C.m, p = C.p, tid = threadIdx.x;
   const int nb = partition_bounded<T>(C, kappa);
   const int ne = C.iflag[1];
+  QPK_PT(C, PH_PART);
   // weights E/D for eliminated rows (stored in t1 temporarily)
   for (int i = tid; i < m; i += T) C.t1[i] = C.E[i] / C.D[i];
   __syncthreads();
   const int N = n + nb + p;
   bool reg = false;
-  const bool ok = factor_bounded<T>(C, nb, ne, C.t1, delta_reg, &reg);
+  const bool ok = factor_bounded<T, RPL>(C, nb, ne, C.t1, delta_reg, &reg);
   const double dn = n, dm = m, dp = p, dN = N;
   work += 2.0 * dn * dn + 4.0 * dm * dn + 4.0 * dp * dn;            // residuals
   work += (double)ne * dn * (dn + 1.0) + dN * dN * dN / 3.0;        // assembly + factor
@@ -1051,18 +1233,22 @@ __device__ __noinline__ int newton_bounded(CT &C, float &kappa, int kt_mode, flo
   if (!ok) { *stage = SG_PRED; return ST_FACT; }
   make_dinv<T>(C, N);
   rhs_bounded<T>(C, nb, kappa, nullptr, nullptr, nullptr, false);
+  QPK_PT(C, PH_RHS);
   const int nref = reg ? max(refine_steps, 2) : refine_steps;
   if (nref) {
     for (int j = tid; j < N; j += T) { C.w0[j] = C.u0[j]; C.w1[j] = C.u1[j]; }
     __syncthreads();
   }
   solve2<T, RPL>(C, N, true);
+  QPK_PT(C, PH_SOLVE);
   if (nref) {
     refine<T, RPL>(C, nb, true, C.w0, C.u0, nref);
     refine<T, RPL>(C, nb, true, C.w1, C.u1, nref);
     work += 2.0 * nref * (2.0 * dN * dN + 4.0 * dm * dn + 2.0 * dn * dn + 4.0 * dp * dn);
   }
+  QPK_PT(C, PH_REFINE);
   recover_bounded<T>(C, nb, true);
+  QPK_PT(C, PH_RECOVER);
   // predictor step length (kappa_target = 0) and kappa_aff
   float kt;
   if (kt_mode == 0) {
@@ -1122,13 +1308,16 @@ __device__ __noinline__ int newton_bounded(CT &C, float &kappa, int kt_mode, flo
   }
   kappa = knew;
   __syncthreads();
+  QPK_PT(C, PH_STEP);
   return ST_CONV;
 }
 
 // One Mehrotra predictor-corrector iteration of the standard form.
 template <int T, int RPL, class CT>
-__device__ __noinline__ int newton_standard(CT &C, float mu, int kt_mode, float kr, float delta_reg, double &work,
+__device__ __noinline__ int newton_standard(CT &Cin_, float mu, int kt_mode, float kr, float delta_reg, double &work,
                         int *stage) {
+  CT C = uctx(Cin_);
+  mu = rflf(mu); kt_mode = rfl(kt_mode); kr = rflf(kr); delta_reg = rflf(delta_reg);
   const int n = C.n, m = C.m, p = C.p, tid = threadIdx.x;
   float bad[1] = {0.f};
   for (int i = tid; i < m; i += T) {
@@ -1145,7 +1334,7 @@ __device__ __noinline__ int newton_standard(CT &C, float mu, int kt_mode, float 
   __syncthreads();
   const int N = n + p;
   assemble<T>(C, 0, ne, C.E, false, delta_reg);
-  const bool ok = signed_cholesky<T>(C.M, C.ld, N, n, C.iflag, C.pan);
+  const bool ok = signed_cholesky<T, RPL>(C.M, N, n, C.iflag);
   const double dn = n, dm = m, dp = p, dN = N;
   work += 2.0 * dn * dn + 4.0 * dm * dn + 4.0 * dp * dn;
   work += dm * dn * (dn + 1.0) + dN * dN * dN / 3.0;
@@ -1252,6 +1441,7 @@ QPD int newton_loop(CT &C, bool bounded, int max_iter, float tol, int kt_mode, f
     float kappa = m ? sm[0] / (float)m : 0.f;
     bool bad = false;
     res = residuals<T>(C, bounded, kappa, kt_mode == 2 ? kr : 0.f, &bad);
+    QPK_PT(C, PH_RESID);
     if (bad || !finitef(res)) {
       status = ST_NONFIN;
       stage = kt_mode == 2 ? SG_RELAX : (it == 0 ? SG_NONE : SG_LS);
@@ -1282,8 +1472,11 @@ QPD void load_vectors(CT &C) {
 // Factor at the current (relaxed) point and solve the adjoint system for
 // the upstream gradient; returns dx in u0[0:n], dy in u0[n+nb:], dz in dv0.
 template <int T, int RPL, class CT>
-__device__ __noinline__ bool adjoint(CT &C, bool bounded, const gf *gx, const gf *gy, const gf *gz,
+__device__ __noinline__ bool adjoint(CT &Cin_, bool bounded, const gf *gx, const gf *gy, const gf *gz,
                  float delta_reg, int refine_steps, double &work) {
+  CT C = uctx(Cin_);
+  bounded = rfl(bounded); gx = rflp(gx); gy = rflp(gy); gz = rflp(gz);
+  delta_reg = rflf(delta_reg); refine_steps = rfl(refine_steps);
   const int n = C.n, m = C.m, p = C.p, tid = threadIdx.x;
   float sm[1] = {0.f};
   for (int i = tid; i < m; i += T) {
@@ -1314,10 +1507,10 @@ __device__ __noinline__ bool adjoint(CT &C, bool bounded, const gf *gx, const gf
   const int N = n + nb + p;
   bool ok, reg = false;
   if (bounded) {
-    ok = factor_bounded<T>(C, nb, ne, C.t1, delta_reg, &reg);
+    ok = factor_bounded<T, RPL>(C, nb, ne, C.t1, delta_reg, &reg);
   } else {
     assemble<T>(C, nb, ne, C.t1, false, 0.f);
-    ok = signed_cholesky<T>(C.M, C.ld, N, n, C.iflag, C.pan);
+    ok = signed_cholesky<T, RPL>(C.M, N, n, C.iflag);
   }
   const int nref = refine_steps + 2;
   const double dn = n, dN = N;
@@ -1380,7 +1573,8 @@ __device__ __noinline__ bool adjoint(CT &C, bool bounded, const gf *gx, const gf
 
 // Write the parameter gradients of Algorithm 3 with coalesced stores.
 template <int T, class CT>
-__device__ __noinline__ void write_grads(CT &C, const Params &P, size_t qi) {
+__device__ __noinline__ void write_grads(CT &Cin_, const Params &P, size_t qi) {
+  CT C = uctx(Cin_);
   const int n = C.n, m = C.m, p = C.p, tid = threadIdx.x;
   const lf *dx = C.u0, *dy = C.u0 + n, *dz = C.dv0;
   if (P.dQ) {
@@ -1423,30 +1617,91 @@ template <int T, int RPL, bool MLDS, int MODE>
 QPD void qp_body(const Params &P) {
   extern __shared__ __attribute__((aligned(16))) float smem[];
   typedef typename std::conditional<MLDS, lf, gf>::type MF;
-  const int n = P.n, m = P.m, p = P.p;
-  const Layout L = make_layout(n, m, p, P.kb, MLDS);
   const size_t qi = blockIdx.x;
+  // sizes and data pointers: from the batch (solve / backward) or from this
+  // block's slot descriptor (serving step)
+  int n, m, p, kb;
+  const float *Qp, *qp, *Ap, *bp, *Gp, *hp;
+  float *wsp;
+  if constexpr (MODE == kServe) {
+    const SlotDesc &d = P.desc[qi];
+    n = d.n; m = d.m; p = d.p; kb = d.kb;
+    Qp = d.Q; qp = d.q; Ap = d.A; bp = d.b; Gp = d.G; hp = d.h;
+    wsp = d.ws;
+  } else {
+    n = P.n; m = P.m; p = P.p; kb = P.kb;
+    Qp = P.Q + qi * (size_t)n * n;
+    qp = P.q + qi * (size_t)n;
+    Ap = p ? P.A + qi * (size_t)p * n : nullptr;
+    bp = p ? P.b + qi * (size_t)p : nullptr;
+    Gp = m ? P.G + qi * (size_t)m * n : nullptr;
+    hp = m ? P.h + qi * (size_t)m : nullptr;
+    wsp = MLDS ? nullptr : P.ws + (size_t)qi * P.ws_stride;
+  }
+  const Layout L = make_layout(n, m, p, kb, MLDS);
   lf *sm = (lf *)smem;
   MF *Mp;
   if constexpr (MLDS) Mp = sm + L.M;
-  else Mp = (gf *)P.ws + (size_t)qi * P.ws_stride;
+  else Mp = (gf *)wsp;
   Ctx<MF> C;
   init_ctx(C, sm, L, Mp);
-  C.Q = (const gf *)P.Q + qi * (size_t)n * n;
-  C.q_g = (const gf *)P.q + qi * (size_t)n;
-  C.A = p ? (const gf *)P.A + qi * (size_t)p * n : nullptr;
-  C.b_g = p ? (const gf *)P.b + qi * (size_t)p : nullptr;
-  C.G = m ? (const gf *)P.G + qi * (size_t)m * n : nullptr;
-  C.h_g = m ? (const gf *)P.h + qi * (size_t)m : nullptr;
+  C.Q = (const gf *)Qp;
+  C.q_g = (const gf *)qp;
+  C.A = (const gf *)Ap;
+  C.b_g = (const gf *)bp;
+  C.G = (const gf *)Gp;
+  C.h_g = (const gf *)hp;
   const int tid = threadIdx.x;
   const bool bounded = P.form == 0;
+#ifdef QPK_PHASE_TIMING
+  __shared__ long long pt_acc[PH_N];
+  C.pt = (__attribute__((address_space(3))) long long *)pt_acc;
+  if (tid < PH_N) C.pt[tid] = 0;
+  __syncthreads();
+  if (tid == 0) C.pt[15] = clock64();
+#endif
   load_vectors<T>(C);
   double work = 0.0;
   int iters = 0;
   float res = 0.f;
   int status;
-  if constexpr (MODE == kSolve) {
+  if constexpr (MODE == kServe) {
+    // resume one resident QP for at most max_iter Newton iterations; the
+    // iterate (x, y, z, s) persists in the slot's state between steps
+    const SlotDesc &d = P.desc[qi];
+    gf *st = (gf *)d.state;
+    bool ok = true;
+    if (d.flags & 1) {
+      ok = initialize<T, RPL>(C, work);
+    } else {
+      for (int i = tid; i < n; i += T) C.x[i] = st[i];
+      for (int k = tid; k < p; k += T) C.y[k] = st[n + k];
+      for (int i = tid; i < m; i += T) {
+        C.z[i] = st[n + p + i];
+        C.s[i] = st[n + p + m + i];
+      }
+      __syncthreads();
+    }
+    if (!ok) {
+      status = mkstatus(ST_FACT, SG_PRED);
+    } else {
+      status = newton_loop<T, RPL>(C, bounded, P.max_iter, P.tol, P.pc ? 0 : 1, P.sigma, 0.f,
+                                   P.delta_reg, P.refine, work, iters, res);
+    }
+    for (int i = tid; i < n; i += T) st[i] = C.x[i];
+    for (int k = tid; k < p; k += T) st[n + k] = C.y[k];
+    for (int i = tid; i < m; i += T) {
+      st[n + p + i] = C.z[i];
+      st[n + p + m + i] = C.s[i];
+    }
+    if (tid == 0) {
+      *d.status = status;
+      *d.iters = iters;
+      *d.res = res;
+    }
+  } else if constexpr (MODE == kSolve) {
     const bool ok = initialize<T, RPL>(C, work);
+    QPK_PT(C, PH_INIT);
     if (!ok) {
       status = mkstatus(ST_FACT, SG_PRED);
       res = __int_as_float(0x7fc00000);
@@ -1482,6 +1737,7 @@ QPD void qp_body(const Params &P) {
     const gf *gy = P.gy ? (const gf *)P.gy + qi * (size_t)p : nullptr;
     const gf *gz = P.gz ? (const gf *)P.gz + qi * (size_t)m : nullptr;
     const bool ok = adjoint<T, RPL>(C, bounded, gx, gy, gz, P.delta_reg, P.refine, work);
+    QPK_PT(C, PH_BWD);
     if (!ok) status = mkstatus(ST_FACT, SG_BWD);
     __syncthreads();
     write_grads<T>(C, P, qi);
@@ -1495,19 +1751,29 @@ QPD void qp_body(const Params &P) {
       if (P.work) P.work[qi] = work;
     }
   }
+#ifdef QPK_PHASE_TIMING
+  QPK_PT(C, PH_OUT);
+  if (P.phase && tid < PH_N - 1) P.phase[qi * PH_N + tid] = C.pt[tid];
+#endif
 }
 
 // One workgroup per QP: Algorithm 1 (or the standard IPM) end to end.
 template <int T, int RPL, bool MLDS>
-__global__ void __launch_bounds__(T, (T >= 256 ? 2 : 4)) qp_solve_kernel(Params P) {
+__global__ void __launch_bounds__(T, (T >= 512 ? 2 : (T >= 256 ? 3 : 4))) qp_solve_kernel(Params P) {
   qp_body<T, RPL, MLDS, kSolve>(P);
 }
 
 // One workgroup per QP: relax (Algorithm 2), adjoint solve and parameter
 // gradients (Algorithm 3).
 template <int T, int RPL, bool MLDS>
-__global__ void __launch_bounds__(T, (T >= 256 ? 2 : 4)) qp_backward_kernel(Params P) {
+__global__ void __launch_bounds__(T, (T >= 512 ? 2 : (T >= 256 ? 3 : 4))) qp_backward_kernel(Params P) {
   qp_body<T, RPL, MLDS, kBackward>(P);
+}
+
+// One workgroup per resident serving slot: resume its Newton loop.
+template <int T, int RPL, bool MLDS>
+__global__ void __launch_bounds__(T, (T >= 512 ? 2 : (T >= 256 ? 3 : 4))) qp_serve_kernel(Params P) {
+  qp_body<T, RPL, MLDS, kServe>(P);
 }
 
 template <class K>
@@ -1525,6 +1791,10 @@ hipError_t launch_t(const Params &P, bool m_in_lds, size_t lds, int grid, hipStr
   if (P.mode == kSolve) {
     if (m_in_lds) return launch_k(qp_solve_kernel<T, RPL, true>, P, T, lds, grid, st);
     return launch_k(qp_solve_kernel<T, RPL, false>, P, T, lds, grid, st);
+  }
+  if (P.mode == kServe) {
+    if (m_in_lds) return launch_k(qp_serve_kernel<T, RPL, true>, P, T, lds, grid, st);
+    return launch_k(qp_serve_kernel<T, RPL, false>, P, T, lds, grid, st);
   }
   if (m_in_lds) return launch_k(qp_backward_kernel<T, RPL, true>, P, T, lds, grid, st);
   return launch_k(qp_backward_kernel<T, RPL, false>, P, T, lds, grid, st);

@@ -10,7 +10,7 @@ size_t lds_bytes(int n, int m, int p, int kb, bool m_in_lds) {
 
 int64_t ws_floats(int n, int m, int p, int kb) {
   const Layout L = make_layout(n, m, p, kb, false);
-  return (int64_t)L.Nmax * L.ld + 4;
+  return (int64_t)al4(moff(L.Nmax) + 16);
 }
 
 size_t lds_limit() { return 160 * 1024; }
