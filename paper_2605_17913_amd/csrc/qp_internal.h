@@ -61,7 +61,7 @@ struct SlotDesc {
 
 // Bytes of dynamic LDS a launch needs, and whether the factor matrix M
 // lives in LDS.  Returns 0 if the configuration is unsupported.
-size_t lds_bytes(int n, int m, int p, int kb, bool m_in_lds);
+size_t lds_bytes(int n, int m, int p, int kb, bool m_in_lds, int threads);
 // Floats of global factor storage per QP when M is not in LDS.
 int64_t ws_floats(int n, int m, int p, int kb);
 // Largest dynamic LDS per block the kernels may use on this device.
@@ -99,14 +99,14 @@ inline int make_plan(int n, int m, int p, const qp_opts &o, Plan *pl) {
   if (T != 128 && T != 256 && T != 512) return QPX_ERR_ARG;
   pl->threads = T;
   const size_t lim = qpk::lds_limit();
-  const size_t with_m = qpk::lds_bytes(n, m, p, kb, true);
+  const size_t with_m = qpk::lds_bytes(n, m, p, kb, true, T);
   if (with_m <= lim) {
     pl->m_in_lds = true;
     pl->lds = with_m;
     pl->ws_stride = 0;
   } else {
     pl->m_in_lds = false;
-    pl->lds = qpk::lds_bytes(n, m, p, kb, false);
+    pl->lds = qpk::lds_bytes(n, m, p, kb, false, T);
     if (pl->lds > lim) return QPX_ERR_UNSUPPORTED;
     pl->ws_stride = qpk::ws_floats(n, m, p, kb);
   }

@@ -185,7 +185,7 @@ struct Layout {
   int x, y, z, s, v, q, h, b;
   int E, D, c;
   int rt, ri, re, rz, rs;
-  int tQ, tGz, tAy;
+  int tGz, tAy;
   int t0, t1, u0, u1, dv0, dv1, dinv;
   int part, red;
   int w0, w1, rr, dd;  // rhs copies / residual for refinement; FP64 scratch
@@ -197,7 +197,7 @@ struct Layout {
 
 __host__ __device__ inline int al4(int a) { return (a + 3) & ~3; }
 
-__host__ __device__ inline Layout make_layout(int n, int m, int p, int kb, bool m_lds) {
+__host__ __device__ inline Layout make_layout(int n, int m, int p, int kb, bool m_lds, int T) {
   Layout L;
   L.n = n; L.m = m; L.p = p; L.kb = kb;
   L.Nmax = n + kb + p;
@@ -208,13 +208,15 @@ __host__ __device__ inline Layout make_layout(int n, int m, int p, int kb, bool 
   L.q = take(n); L.h = take(m); L.b = take(p);
   L.E = take(m); L.D = take(m); L.c = take(m);
   L.rt = take(n); L.ri = take(m); L.re = take(p); L.rz = take(m); L.rs = take(m);
-  L.tQ = take(n); L.tGz = take(n); L.tAy = take(n);
-  L.t0 = take(m > p ? m : p); L.t1 = take(m > p ? m : p);
+  L.tGz = take(n); L.tAy = take(n);
+  const int tlen = max(max(m, p), L.Nmax);  // t0/t1 also hold refinement rhs copies
+  L.t0 = take(tlen); L.t1 = take(tlen);
   L.u0 = take(L.Nmax); L.u1 = take(L.Nmax);
   L.dv0 = take(m); L.dv1 = take(m); L.dinv = take(L.Nmax);
-  L.part = take(1024); L.red = take(16 * 32);
-  L.w0 = take(L.Nmax); L.w1 = take(L.Nmax); L.rr = take(L.Nmax);
-  L.dd = take(2 * (2 * m + p + 3 * n + 8));
+  // partial sums (2 floats or 1 double per thread) and reduction scratch
+  L.part = take(2 * T); L.red = take((T / 64) * 16);
+  L.w0 = L.t0; L.w1 = L.t1; L.rr = take(L.Nmax);
+  L.dd = take(2 * (2 * m + p + n + 8));
   L.pan = take(4);
   L.role = take(m); L.bidx = take(m); L.elist = take(m); L.iflag = take(16);
   if (m_lds) { L.M = o; o += al4(moff(L.Nmax) + 16); } else { L.M = -1; }
@@ -261,7 +263,7 @@ QPD void rowdot(const RF *R, int ld, int rows, int cols, const lf *const (&x)[NV
 template <int T, int NV, class RF>
 QPD void coldot(const RF *R, int ld, int rows, int cols, const lf *const (&x)[NV],
                 lf *const (&out)[NV], lf *part) {
-  static_assert(NV * T <= 1024, "part too small");
+  static_assert(NV <= 2, "part holds two floats per thread");
   const int cw = cols <= 64 ? 64 : (cols <= 128 ? (T >= 128 ? 128 : 64) : (T >= 256 ? 256 : T));
   const int groups = T / cw;
   const int g = threadIdx.x / cw, jl = threadIdx.x % cw;
@@ -548,8 +550,9 @@ QPD void rowdot_d(const RF *R, int ld, int rows, int cols, const lf *x, ldd *out
 
 // FP64-accumulated out[j] (+)= sum_i R[i*ld + j] x[i]; barriers inside.
 template <int T, class RF, class XF>
-QPD void coldot_d(const RF *R, int ld, int rows, int cols, const XF *x, ldd *out, bool add,
-                  ldd *part) {
+QPD float coldot_d(const RF *R, int ld, int rows, int cols, const XF *x, ldd *out, bool add,
+                   ldd *part) {
+  float mx = 0.f;  // largest |column sum| this thread produced
   const int cw = cols <= 64 ? 64 : (cols <= 128 ? (T >= 128 ? 128 : 64) : (T >= 256 ? 256 : T));
   const int groups = T / cw;
   const int g = threadIdx.x / cw, jl = threadIdx.x % cw;
@@ -564,9 +567,11 @@ QPD void coldot_d(const RF *R, int ld, int rows, int cols, const XF *x, ldd *out
       double s = 0.0;
       for (int gg = 0; gg < groups; ++gg) s += part[gg * cw + jl];
       out[j] = add ? out[j] + s : s;
+      mx = fmaxf(mx, fabsf((float)s));
     }
     __syncthreads();
   }
+  return mx;
 }
 
 // ---------------------------------------------------------------------------
@@ -583,7 +588,7 @@ struct Ctx {
   lf *x, *y, *z, *s, *v, *q, *h, *b;
   lf *E, *D, *c;
   lf *rt, *ri, *re, *rz, *rs;
-  lf *tQ, *tGz, *tAy;
+  lf *tGz, *tAy;
   lf *t0, *t1, *u0, *u1, *dv0, *dv1, *dinv;
   lf *part, *red;
   lf *w0, *w1, *rr, *pan;
@@ -602,7 +607,7 @@ QPD void init_ctx(Ctx<MF> &C, lf *sm, const Layout &L, MF *Mptr) {
   C.q = sm + L.q; C.h = sm + L.h; C.b = sm + L.b;
   C.E = sm + L.E; C.D = sm + L.D; C.c = sm + L.c;
   C.rt = sm + L.rt; C.ri = sm + L.ri; C.re = sm + L.re; C.rz = sm + L.rz; C.rs = sm + L.rs;
-  C.tQ = sm + L.tQ; C.tGz = sm + L.tGz; C.tAy = sm + L.tAy;
+  C.tGz = sm + L.tGz; C.tAy = sm + L.tAy;
   C.t0 = sm + L.t0; C.t1 = sm + L.t1; C.u0 = sm + L.u0; C.u1 = sm + L.u1;
   C.dv0 = sm + L.dv0; C.dv1 = sm + L.dv1; C.dinv = sm + L.dinv;
   C.part = sm + L.part; C.red = sm + L.red;
@@ -628,7 +633,7 @@ QPD Ctx<MF> uctx(const Ctx<MF> &I) {
   C.q = rflp(I.q); C.h = rflp(I.h); C.b = rflp(I.b);
   C.E = rflp(I.E); C.D = rflp(I.D); C.c = rflp(I.c);
   C.rt = rflp(I.rt); C.ri = rflp(I.ri); C.re = rflp(I.re); C.rz = rflp(I.rz); C.rs = rflp(I.rs);
-  C.tQ = rflp(I.tQ); C.tGz = rflp(I.tGz); C.tAy = rflp(I.tAy);
+  C.tGz = rflp(I.tGz); C.tAy = rflp(I.tAy);
   C.t0 = rflp(I.t0); C.t1 = rflp(I.t1); C.u0 = rflp(I.u0); C.u1 = rflp(I.u1);
   C.dv0 = rflp(I.dv0); C.dv1 = rflp(I.dv1); C.dinv = rflp(I.dinv);
   C.part = rflp(I.part); C.red = rflp(I.red);
@@ -649,28 +654,24 @@ __device__ __noinline__ float residuals(CT &Cin_, bool bounded, float kappa, flo
   const int n = C.n, m = C.m, p = C.p, tid = threadIdx.x;
   // matrix-vector products accumulated in FP64 (the FP32 iterate is exact
   // in FP64, so the residual is limited only by the iterate's rounding)
-  ldd *gxd = C.dd, *axd = C.dd + m, *qxd = C.dd + m + p, *gzd = qxd + n, *ayd = gzd + n;
+  // one FP64 accumulator for Qx + G'z + A'y; the pieces' norms are taken
+  // as they are produced
+  ldd *gxd = C.dd, *axd = C.dd + m, *rtd = C.dd + m + p;
   ldd *pd = reinterpret_cast<ldd *>(C.part);
   if (m) rowdot_d<T>(C.G, n, m, n, C.x, gxd);
   if (p) rowdot_d<T>(C.A, n, p, n, C.x, axd);
-  coldot_d<T>(C.Q, n, n, n, C.x, qxd, false, pd);
-  if (m) coldot_d<T>(C.G, n, m, n, C.z, gzd, false, pd);
-  if (p) coldot_d<T>(C.A, n, p, n, C.y, ayd, false, pd);
-  // max-norm accumulators
   enum { RT, QX, QQ, GZ, AY, RI, GX, SS, HH, RE, AX, BB, RZS, ZZ, CC, NF, NK };
   float mx[NK];
 #pragma unroll
   for (int k = 0; k < NK; ++k) mx[k] = 0.f;
+  mx[QX] = coldot_d<T>(C.Q, n, n, n, C.x, rtd, false, pd);
+  if (m) mx[GZ] = coldot_d<T>(C.G, n, m, n, C.z, rtd, true, pd);
+  if (p) mx[AY] = coldot_d<T>(C.A, n, p, n, C.y, rtd, true, pd);
   for (int i = tid; i < n; i += T) {
-    const double gz = m ? gzd[i] : 0.0, ay = p ? ayd[i] : 0.0;
-    const double rd = qxd[i] + (double)C.q[i] + gz + ay;
-    const float r = (float)rd;
+    const float r = (float)(rtd[i] + (double)C.q[i]);
     C.rt[i] = r;
     mx[RT] = fmaxf(mx[RT], fabsf(r));
-    mx[QX] = fmaxf(mx[QX], fabsf((float)qxd[i]));
     mx[QQ] = fmaxf(mx[QQ], fabsf(C.q[i]));
-    mx[GZ] = fmaxf(mx[GZ], fabsf((float)gz));
-    mx[AY] = fmaxf(mx[AY], fabsf((float)ay));
     if (!finitef(r)) mx[NF] = 1.f;
   }
   for (int i = tid; i < m; i += T) {
@@ -1638,7 +1639,7 @@ QPD void qp_body(const Params &P) {
     hp = m ? P.h + qi * (size_t)m : nullptr;
     wsp = MLDS ? nullptr : P.ws + (size_t)qi * P.ws_stride;
   }
-  const Layout L = make_layout(n, m, p, kb, MLDS);
+  const Layout L = make_layout(n, m, p, kb, MLDS, T);
   lf *sm = (lf *)smem;
   MF *Mp;
   if constexpr (MLDS) Mp = sm + L.M;

@@ -4,12 +4,12 @@
 
 namespace qpk {
 
-size_t lds_bytes(int n, int m, int p, int kb, bool m_in_lds) {
-  return (size_t)make_layout(n, m, p, kb, m_in_lds).total * sizeof(float);
+size_t lds_bytes(int n, int m, int p, int kb, bool m_in_lds, int threads) {
+  return (size_t)make_layout(n, m, p, kb, m_in_lds, threads).total * sizeof(float);
 }
 
 int64_t ws_floats(int n, int m, int p, int kb) {
-  const Layout L = make_layout(n, m, p, kb, false);
+  const Layout L = make_layout(n, m, p, kb, false, 128);
   return (int64_t)al4(moff(L.Nmax) + 16);
 }
 
