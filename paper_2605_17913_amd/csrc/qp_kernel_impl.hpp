@@ -189,7 +189,8 @@ struct Layout {
   int t0, t1, u0, u1, dv0, dv1, dinv;
   int part, red;
   int w0, w1, rr, dd;  // rhs copies / residual for refinement; FP64 scratch
-  int pan;             // panel staging buffer (factor in global memory)
+  int pan;             // (unused)
+  int zrow;            // a row of kNB zeros
   int role, bidx, elist, iflag;
   int M;      // offset of M if in LDS, else -1
   int total;  // floats
@@ -218,6 +219,7 @@ __host__ __device__ inline Layout make_layout(int n, int m, int p, int kb, bool 
   L.w0 = L.t0; L.w1 = L.t1; L.rr = take(L.Nmax);
   L.dd = take(2 * (2 * m + p + n + 8));
   L.pan = take(4);
+  L.zrow = take(kNB);  // 16 zeros for the triangular solves
   L.role = take(m); L.bidx = take(m); L.elist = take(m); L.iflag = take(16);
   if (m_lds) { L.M = o; o += al4(moff(L.Nmax) + 16); } else { L.M = -1; }
   L.total = o;
@@ -232,6 +234,7 @@ template <int T, int NV, class RF>
 QPD void rowdot(const RF *R, int ld, int rows, int cols, const lf *const (&x)[NV],
                 lf *const (&out)[NV]) {
   const int sub = threadIdx.x & 15, grp = threadIdx.x >> 4;
+#pragma unroll 2
   for (int i0 = 0; i0 < rows; i0 += T / 16) {
     const int i = i0 + grp;
     float acc[NV];
@@ -239,6 +242,7 @@ QPD void rowdot(const RF *R, int ld, int rows, int cols, const lf *const (&x)[NV
     for (int k = 0; k < NV; ++k) acc[k] = 0.f;
     if (i < rows) {
       const RF *Ri = R + (size_t)i * ld;
+#pragma unroll 4
       for (int j = sub; j < cols; j += 16) {
         const float r = Ri[j];
 #pragma unroll
@@ -273,6 +277,7 @@ QPD void coldot(const RF *R, int ld, int rows, int cols, const lf *const (&x)[NV
 #pragma unroll
     for (int k = 0; k < NV; ++k) acc[k] = 0.f;
     if (j < cols) {
+#pragma unroll 8
       for (int i = g; i < rows; i += groups) {
         const float r = R[(size_t)i * ld + j];
 #pragma unroll
@@ -354,16 +359,23 @@ __device__ __noinline__ bool signed_cholesky(MF *M, int N, int npos, li *flag) {
           }
         }
       }
-      // write back whole 16-column segments (entries right of the diagonal
-      // of the diagonal block land in the row's padding and are never read)
+      // write back whole 16-column segments; entries right of the diagonal
+      // (the row's padding inside the diagonal block) are set to exact zeros,
+      // which the triangular solves rely on
 #pragma unroll
       for (int t = 0; t < RPL; ++t) {
-        const int i = k0 + lane + 64 * t;
+        const int r = lane + 64 * t, i = k0 + r;
         if (i < N) {
           MF *row = M + moff(i) + k0;
 #pragma unroll
-          for (int c = 0; c < kNB; c += 4)
-            *reinterpret_cast<V4 *>(row + c) = f4v{P[t][c], P[t][c + 1], P[t][c + 2], P[t][c + 3]};
+          for (int c = 0; c < kNB; c += 4) {
+            f4v v4;
+            v4.x = (c + 0 <= r) ? P[t][c + 0] : 0.f;
+            v4.y = (c + 1 <= r) ? P[t][c + 1] : 0.f;
+            v4.z = (c + 2 <= r) ? P[t][c + 2] : 0.f;
+            v4.w = (c + 3 <= r) ? P[t][c + 3] : 0.f;
+            *reinterpret_cast<V4 *>(row + c) = v4;
+          }
         }
       }
       if (fail && lane == 0) *flag = 1;
@@ -442,21 +454,22 @@ __device__ __noinline__ bool signed_cholesky(MF *M, int N, int npos, li *flag) {
 // rows lane + 64 t).  Uses the L' copy in the strict upper triangle for the
 // forward sweep and L's rows for the backward sweep; dinv[j] = 1 / L[j][j].
 template <int RPL, class MF>
-QPD void signed_solve_wave(const MF *M, int N, int npos, const lf *dinv, lf *r) {
+QPD void signed_solve_wave(const MF *M, int N, int npos, const lf *dinv, lf *r, const lf *zrow) {
   typedef typename Vec4<const MF>::type CV4;
   static_assert(kNB % RPL == 0, "row slot must be static within a block");
   const int lane = threadIdx.x & 63;
-  // lane l owns rows RPL*l + t, so row j sits in lane j/RPL, slot j%RPL
+  // lane l owns rows RPL*l + t, so row j sits in lane j/RPL, slot j%RPL.
+  // The factor holds exact zeros right of the diagonal inside every row's
+  // padded 16-column segment; rows that must not be touched in a block read
+  // the zero row `zrow` instead, so no per-step masking is needed.  The
+  // diagonal entry is applied by overwriting the owner's value after the FMA.
   float a[RPL];
 #pragma unroll
   for (int t = 0; t < RPL; ++t) {
     const int i = RPL * lane + t;
     a[t] = i < N ? r[i] : 0.f;
   }
-  // Forward sweep L w = r, column oriented: once w_j = a_j / L[j][j] is
-  // known every row i > j subtracts L[i][j] w_j.  Per 16-column block each
-  // lane loads its rows' segments L[i][j0..j0+15] (contiguous) with entries
-  // on and right of the diagonal zeroed; the owning lane stores w_j.
+  // forward sweep L w = r: w_j = a_j / L[j][j], then a_i -= L[i][j] w_j, i > j
 #pragma unroll 1
   for (int j0 = 0; j0 < N; j0 += kNB) {
     float Lc[RPL][kNB], dv[kNB];
@@ -464,16 +477,13 @@ QPD void signed_solve_wave(const MF *M, int N, int npos, const lf *dinv, lf *r) 
     for (int t = 0; t < RPL; ++t) {
       const int i = RPL * lane + t;
       const bool in = i >= j0 && i < N;
-      const MF *row = M + moff(in ? i : j0) + j0;
+      // rows below the block: L[i][j0..j0+15]; rows in the block: their
+      // lower part with zeros right of the diagonal; finished rows: zeros
+      const MF *row = in ? M + moff(i) + j0 : (const MF *)zrow;
 #pragma unroll
       for (int c = 0; c < kNB; c += 4) {
         const f4v v4 = *reinterpret_cast<CV4 *>(row + c);
         Lc[t][c] = v4.x; Lc[t][c + 1] = v4.y; Lc[t][c + 2] = v4.z; Lc[t][c + 3] = v4.w;
-      }
-#pragma unroll
-      for (int c = 0; c < kNB; ++c) {
-        const int col = j0 + c;
-        Lc[t][c] = (in && col < i) ? Lc[t][c] : 0.f;
       }
     }
 #pragma unroll
@@ -495,9 +505,7 @@ QPD void signed_solve_wave(const MF *M, int N, int npos, const lf *dinv, lf *r) 
     const int i = RPL * lane + t;
     if (i >= npos) a[t] = -a[t];
   }
-  // Backward sweep L' u = w: once u_j = a_j / L[j][j] is known every row
-  // i < j subtracts L[j][i] u_j; row j of L is read across the lanes (RPL
-  // contiguous floats per lane); the owning lane stores u_j.
+  // backward sweep L' u = w: u_j = a_j / L[j][j], then a_i -= L[j][i] u_j, i < j
 #pragma unroll 1
   for (int b0 = ((N - 1) / kNB) * kNB; b0 >= 0; b0 -= kNB) {
     float Lr[RPL][kNB], dv[kNB];
@@ -508,8 +516,9 @@ QPD void signed_solve_wave(const MF *M, int N, int npos, const lf *dinv, lf *r) 
 #pragma unroll
       for (int t = 0; t < RPL; ++t) {
         const int i = RPL * lane + t;
-        const float v = row[min(i, j)];
-        Lr[t][c] = (b0 + c < N && i < j) ? v : 0.f;
+        // rows above the block read row j; rows in the block read row j's
+        // zero padding right of its diagonal; rows below read zeros
+        Lr[t][c] = i < b0 + kNB ? row[i] : zrow[c];
       }
       dv[c] = dinv[j];
     }
@@ -535,11 +544,13 @@ QPD void signed_solve_wave(const MF *M, int N, int npos, const lf *dinv, lf *r) 
 template <int T, class RF>
 QPD void rowdot_d(const RF *R, int ld, int rows, int cols, const lf *x, ldd *out) {
   const int sub = threadIdx.x & 15, grp = threadIdx.x >> 4;
+#pragma unroll 2
   for (int i0 = 0; i0 < rows; i0 += T / 16) {
     const int i = i0 + grp;
     double acc = 0.0;
     if (i < rows) {
       const RF *Ri = R + (size_t)i * ld;
+#pragma unroll 4
       for (int j = sub; j < cols; j += 16) acc = fma((double)Ri[j], (double)x[j], acc);
     }
 #pragma unroll
@@ -559,8 +570,11 @@ QPD float coldot_d(const RF *R, int ld, int rows, int cols, const XF *x, ldd *ou
   for (int jb = 0; jb < cols; jb += cw) {
     const int j = jb + jl;
     double acc = 0.0;
-    if (j < cols)
+    if (j < cols) {
+      // independent loads first (several in flight), then the FP64 chain
+#pragma unroll 8
       for (int i = g; i < rows; i += groups) acc = fma((double)R[(size_t)i * ld + j], (double)x[i], acc);
+    }
     part[threadIdx.x] = acc;
     __syncthreads();
     if (g == 0 && j < cols) {
@@ -591,7 +605,7 @@ struct Ctx {
   lf *tGz, *tAy;
   lf *t0, *t1, *u0, *u1, *dv0, *dv1, *dinv;
   lf *part, *red;
-  lf *w0, *w1, *rr, *pan;
+  lf *w0, *w1, *rr, *pan, *zrow;
   ldd *dd;
   li *role, *bidx, *elist, *iflag;
   __attribute__((address_space(3))) long long *pt;
@@ -611,7 +625,7 @@ QPD void init_ctx(Ctx<MF> &C, lf *sm, const Layout &L, MF *Mptr) {
   C.t0 = sm + L.t0; C.t1 = sm + L.t1; C.u0 = sm + L.u0; C.u1 = sm + L.u1;
   C.dv0 = sm + L.dv0; C.dv1 = sm + L.dv1; C.dinv = sm + L.dinv;
   C.part = sm + L.part; C.red = sm + L.red;
-  C.w0 = sm + L.w0; C.w1 = sm + L.w1; C.rr = sm + L.rr; C.pan = sm + L.pan;
+  C.w0 = sm + L.w0; C.w1 = sm + L.w1; C.rr = sm + L.rr; C.pan = sm + L.pan; C.zrow = sm + L.zrow;
   C.dd = reinterpret_cast<ldd *>(sm + L.dd);
   C.role = reinterpret_cast<li *>(sm + L.role);
   C.bidx = reinterpret_cast<li *>(sm + L.bidx);
@@ -637,7 +651,7 @@ QPD Ctx<MF> uctx(const Ctx<MF> &I) {
   C.t0 = rflp(I.t0); C.t1 = rflp(I.t1); C.u0 = rflp(I.u0); C.u1 = rflp(I.u1);
   C.dv0 = rflp(I.dv0); C.dv1 = rflp(I.dv1); C.dinv = rflp(I.dinv);
   C.part = rflp(I.part); C.red = rflp(I.red);
-  C.w0 = rflp(I.w0); C.w1 = rflp(I.w1); C.rr = rflp(I.rr); C.pan = rflp(I.pan);
+  C.w0 = rflp(I.w0); C.w1 = rflp(I.w1); C.rr = rflp(I.rr); C.pan = rflp(I.pan); C.zrow = rflp(I.zrow);
   C.dd = rflp(I.dd);
   C.role = rflp(I.role); C.bidx = rflp(I.bidx); C.elist = rflp(I.elist); C.iflag = rflp(I.iflag);
   C.pt = rflp(I.pt);
@@ -860,6 +874,7 @@ __device__ __noinline__ void assemble(CT &Cin_, int nb, int ne, const lf *wts, b
     for (int k0 = 0; k0 < ne; k0 += R) {
       const int kr = min(R, ne - k0);
       __syncthreads();  // the previous chunk has been consumed
+#pragma unroll 4
       for (int e = tid; e < kr * ldg; e += T) {
         const int r = e / ldg, j = e - r * ldg;
         stage[e] = j < n ? C.G[(size_t)C.elist[k0 + r] * n + j] : 0.f;
@@ -938,11 +953,11 @@ __device__ __noinline__ void solve2(CT &Cin_, int N, bool both) {
   N = rfl(N); both = rfl(both);
   const int wid = threadIdx.x >> 6;
   if constexpr (T >= 128) {
-    if (wid == 0) signed_solve_wave<RPL>(C.M, N, C.n, C.dinv, C.u0);
-    else if (wid == 1 && both) signed_solve_wave<RPL>(C.M, N, C.n, C.dinv, C.u1);
+    if (wid == 0) signed_solve_wave<RPL>(C.M, N, C.n, C.dinv, C.u0, C.zrow);
+    else if (wid == 1 && both) signed_solve_wave<RPL>(C.M, N, C.n, C.dinv, C.u1, C.zrow);
   } else {
-    signed_solve_wave<RPL>(C.M, N, C.n, C.dinv, C.u0);
-    if (both) signed_solve_wave<RPL>(C.M, N, C.n, C.dinv, C.u1);
+    signed_solve_wave<RPL>(C.M, N, C.n, C.dinv, C.u0, C.zrow);
+    if (both) signed_solve_wave<RPL>(C.M, N, C.n, C.dinv, C.u1, C.zrow);
   }
   __syncthreads();
 }
@@ -985,7 +1000,7 @@ __device__ __noinline__ void refine(CT &Cin_, int nb, bool bounded, const lf *w,
     }
     for (int a = tid; a < p; a += T) r[n + nb + a] = (float)((double)w[n + nb + a] - ax[a]);
     __syncthreads();
-    if (threadIdx.x < 64) signed_solve_wave<RPL>(C.M, N, n, C.dinv, r);
+    if (threadIdx.x < 64) signed_solve_wave<RPL>(C.M, N, n, C.dinv, r, C.zrow);
     __syncthreads();
     for (int j = tid; j < N; j += T) u[j] += r[j];
     __syncthreads();
@@ -1177,7 +1192,7 @@ __device__ __noinline__ bool initialize(CT &Cin_, double &work) {
   for (int i = tid; i < m; i += T) C.role[i] = -1;
   __syncthreads();
   solve2<T, RPL>(C, N, false);
-  refine<T, RPL>(C, 0, false, C.w0, C.u0, 2);
+  if (m == 0) refine<T, RPL>(C, 0, false, C.w0, C.u0, 2);
   for (int i = tid; i < n; i += T) C.x[i] = C.u0[i];
   for (int k = tid; k < p; k += T) C.y[k] = C.u0[n + k];
   __syncthreads();
@@ -1203,7 +1218,7 @@ __device__ __noinline__ bool initialize(CT &Cin_, double &work) {
   __syncthreads();
   const double dn = n, dm = m, dN = N;
   work += dm * dn * (dn + 1.0) + dN * dN * dN / 3.0 + 2.0 * dN * dN + 4.0 * dm * dn;
-  work += 2.0 * (2.0 * dN * dN + 2.0 * dn * dn + 8.0 * dm * dn);  // two refinement steps
+  if (m == 0) work += 2.0 * (2.0 * dN * dN + 2.0 * dn * dn);  // two refinement steps
   return ok;
 }
 
@@ -1467,6 +1482,7 @@ QPD void load_vectors(CT &C) {
   for (int i = tid; i < C.n; i += T) C.q[i] = C.q_g[i];
   for (int i = tid; i < C.m; i += T) C.h[i] = C.h_g[i];
   for (int i = tid; i < C.p; i += T) C.b[i] = C.b_g[i];
+  if (tid < kNB) C.zrow[tid] = 0.f;
   __syncthreads();
 }
 
