@@ -115,6 +115,86 @@ def serving_bench(n_requests=1200, seed=7, rates=(0.5, 0.9), max_slots=512, iter
     return out
 
 
+def projection_grad_errors(n, n_ineq, n_act, kappa_relax, tol, form, seeds=(0, 1, 2),
+                           ds=None, device="cuda:0"):
+    """Appendix D experiment on the GPU: Euclidean projection onto a polytope
+    (Q = I, q = -x_query, no equalities) with a planted active face; the
+    gradient of v'Pi(x) with respect to x (= -dl/dq for upstream v) is
+    compared with the hard-projection reference J_hard v (eq. hard-jacobian).
+    All (seed, distance) instances of a cell run as one batch.  Returns
+    per-instance relative errors (nan on failure) and the first failing
+    solver stage of each failed instance."""
+    import torch
+    import paper_2605_17913_amd as qpx
+    import qpgen
+    ds = np.logspace(-2, 2, 21) if ds is None else ds
+    insts, vs, ghs = [], [], []
+    for seed in seeds:
+        for k, d in enumerate(ds):
+            P = qpgen.projection(1, n, n_ineq, n_act, float(d), seed * 1000 + k)
+            rng = np.random.default_rng(seed * 7919 + k)
+            v = rng.standard_normal(n).astype(np.float32)
+            Ga = P.G[0, :n_act].astype(np.float64)
+            Jh = np.eye(n) - Ga.T @ np.linalg.solve(Ga @ Ga.T, Ga)
+            insts.append(P)
+            vs.append(v)
+            ghs.append(Jh @ v.astype(np.float64))
+    cat = lambda k: torch.from_numpy(np.concatenate([getattr(P, k) for P in insts])).to(device)
+    Q, q, G, h = cat("Q"), cat("q"), cat("G"), cat("h")
+    sol = qpx.solve(Q, q, None, None, G, h, form=form, tol=tol, max_iter=100)
+    gv = torch.from_numpy(np.stack(vs)).to(device)
+    g = qpx.backward(Q, q, None, None, G, h, sol, gv, form=form, tol=tol,
+                     kappa_relax=kappa_relax, relax_tol=max(tol, 1e-7), relaxed=True)
+    torch.cuda.synchronize()
+    st = sol["status"].cpu().numpy()
+    rs = g["relaxed"]["status"].cpu().numpy()
+    gq = -g["q"].cpu().numpy().astype(np.float64)
+    errs, stages = [], []
+    for k in range(len(insts)):
+        bad_s, bad_r = (st[k] & 0xff) >= 2, (rs[k] & 0xff) >= 2
+        if bad_s or bad_r or not np.all(np.isfinite(gq[k])):
+            errs.append(np.nan)
+            code = st[k] if bad_s else rs[k]
+            stage = (code >> 8) & 0xff if (bad_s or bad_r) else 7
+            stages.append(qpx.STAGES[stage])
+        else:
+            errs.append(float(np.linalg.norm(gq[k] - ghs[k]) / np.linalg.norm(ghs[k])))
+    return np.array(errs), stages
+
+
+def ablation():
+    """Size sweep (kappa_relax = 1e-4, tol 1e-4, #ineq = 1.25 n, active ratio
+    m_r in {0.2, 0.6, 0.8}) and kappa_relax sweep (n = 20, 25 inequalities,
+    10/12/15 active, tol = min(kappa_relax, 1e-4)) for both formulations in
+    FP32, as in the paper's appendix D; medians over 3 seeds x 21 distances."""
+    out = {"size_sweep": [], "kappa_sweep": []}
+    for n in (2, 6, 10, 14, 18, 22, 26, 30, 34, 38):
+        for mr in (0.2, 0.6, 0.8):
+            n_ineq = int(round(1.25 * n))
+            n_act = max(1, int(round(mr * n)))
+            row = {"n": n, "m_r": mr}
+            for form in ("bounded", "standard"):
+                e, st = projection_grad_errors(n, n_ineq, n_act, 1e-4, 1e-4, form)
+                row[form] = {"fail_rate": round(float(np.mean(np.isnan(e))), 3),
+                             "median_err": (round(float(np.nanmedian(e)), 6)
+                                            if np.any(~np.isnan(e)) else None)}
+            out["size_sweep"].append(row)
+    for n_act in (10, 12, 15):
+        for kr in (1e-2, 1e-3, 1e-4, 1e-5, 1e-6, 1e-7, 1e-8, 1e-9):
+            row = {"n_active": n_act, "kappa_relax": kr}
+            for form in ("bounded", "standard"):
+                e, st = projection_grad_errors(20, 25, n_act, kr, min(kr, 1e-4), form)
+                counts = {}
+                for x in st:
+                    counts[x] = counts.get(x, 0) + 1
+                row[form] = {"fail_rate": round(float(np.mean(np.isnan(e))), 3),
+                             "median_err": (round(float(np.nanmedian(e)), 7)
+                                            if np.any(~np.isnan(e)) else None),
+                             "first_failing_stage": counts}
+            out["kappa_sweep"].append(row)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -125,6 +205,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ablation", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--ablation", action="store_true",
+                    help="run the appendix D projection sweeps instead of the benchmark")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -134,6 +216,10 @@ def main():
     import torch
     import paper_2605_17913_amd as qpx
     import qpgen
+
+    if args.ablation:
+        print(json.dumps({"ablation": ablation()}), flush=True)
+        return
 
     B, n, m, p = args.batch, 50, 100, 10
     dev = torch.device("cuda:0")

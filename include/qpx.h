@@ -94,7 +94,27 @@ typedef struct {
   float delta_reg;       /* relative Tikhonov floor on the bordered block (0) */
   int32_t refine_steps;  /* iterative refinement steps of each KKT solve (0)  */
   int32_t block;         /* threads per QP: 0 = automatic, or 128/256/512     */
+  int32_t assembly;      /* arithmetic of H = Q + G_I' diag(w) G_I, one of
+                            QPX_ASM_* below (default QPX_ASM_AUTO)            */
 } qp_opts;
+
+/* Assembly of the (1,1) block of the reduced KKT matrix.  The factorisation,
+ * solves and residuals are FP32 (FP64-accumulated residuals) in every mode.
+ *  QPX_ASM_AUTO    QPX_ASM_BF16X3 for the bounded form when n >= 128 and the
+ *                  staging buffer fits the workgroup's LDS, else QPX_ASM_FP32.
+ *  QPX_ASM_FP32    FP32 fused multiply-adds on the vector ALUs.
+ *  QPX_ASM_BF16X3  matrix cores: each operand split into two bfloat16 terms,
+ *                  three products per pair accumulated in FP32 (relative
+ *                  error about 2^-16 per product); every Newton and adjoint
+ *                  solve then takes at least one step of iterative refinement
+ *                  against the exact operator, which restores FP32 accuracy.
+ *  QPX_ASM_MFMA_FP32  matrix cores with FP32 inputs.
+ * An explicit matrix-core mode for sizes whose staging does not fit returns
+ * QPX_ERR_UNSUPPORTED. */
+#define QPX_ASM_AUTO 0
+#define QPX_ASM_FP32 1
+#define QPX_ASM_BF16X3 2
+#define QPX_ASM_MFMA_FP32 3
 
 typedef struct {
   float *x, *y, *z, *s;  /* [B][n], [B][p], [B][m], [B][m]; y may be NULL iff

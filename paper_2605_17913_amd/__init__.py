@@ -30,6 +30,8 @@ QPX_OK, QPX_PENDING = 0, 1
 CONVERGED, MAX_ITER, NONFINITE, FACTOR_FAIL = 0, 1, 2, 3
 STAGES = ["none", "scaling", "predictor", "centering", "corrector", "linesearch", "relax", "backward"]
 FORMS = {"bounded": 0, "standard": 1}
+# H-block assembly arithmetic (qp_opts.assembly)
+ASSEMBLY = {"auto": 0, "fp32": 1, "bf16x3": 2, "mfma_fp32": 3}
 
 _c_int32, _c_float, _vp = ctypes.c_int32, ctypes.c_float, ctypes.c_void_p
 
@@ -43,7 +45,8 @@ class _Opts(ctypes.Structure):
     _fields_ = [("form", _c_int32), ("max_iter", _c_int32), ("tol", _c_float),
                 ("sigma", _c_float), ("pc", _c_int32), ("kappa_relax", _c_float),
                 ("relax_max_iter", _c_int32), ("relax_tol", _c_float), ("kmax", _c_int32),
-                ("delta_reg", _c_float), ("refine_steps", _c_int32), ("block", _c_int32)]
+                ("delta_reg", _c_float), ("refine_steps", _c_int32), ("block", _c_int32),
+                ("assembly", _c_int32)]
 
 
 class _Out(ctypes.Structure):
@@ -133,9 +136,11 @@ def default_opts() -> _Opts:
 
 def make_opts(form="bounded", tol=None, max_iter=None, sigma=None, pc=None, kappa_relax=None,
               relax_max_iter=None, relax_tol=None, kmax=None, delta_reg=None, refine_steps=None,
-              block=None) -> _Opts:
+              block=None, assembly=None) -> _Opts:
     o = default_opts()
     o.form = FORMS[form] if isinstance(form, str) else int(form)
+    if assembly is not None:
+        o.assembly = ASSEMBLY[assembly] if isinstance(assembly, str) else int(assembly)
     for k, v in dict(tol=tol, max_iter=max_iter, sigma=sigma, kappa_relax=kappa_relax,
                      relax_max_iter=relax_max_iter, relax_tol=relax_tol, kmax=kmax,
                      delta_reg=delta_reg, refine_steps=refine_steps, block=block).items():

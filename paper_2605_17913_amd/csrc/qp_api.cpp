@@ -53,6 +53,7 @@ int check_opts(const qp_opts &o) {
   if (!(o.sigma > 0.f && o.sigma < 1.f)) return QPX_ERR_ARG;
   if (!(o.delta_reg >= 0.f)) return QPX_ERR_ARG;
   if (o.kmax < 0 || o.refine_steps < 0) return QPX_ERR_ARG;
+  if (o.assembly < QPX_ASM_AUTO || o.assembly > QPX_ASM_MFMA_FP32) return QPX_ERR_ARG;
   return QPX_OK;
 }
 
@@ -65,6 +66,7 @@ void fill_common(qpk::Params &P, const qp_batch *bt, const qp_opts &o, const qpk
   P.relax_max_iter = o.relax_max_iter; P.refine = o.refine_steps;
   P.tol = o.tol; P.sigma = o.sigma; P.kappa_relax = o.kappa_relax;
   P.relax_tol = o.relax_tol; P.delta_reg = o.delta_reg;
+  P.asm_mode = pl.amode;
   P.ws = pl.m_in_lds ? nullptr : ctx->ws;
   P.ws_stride = pl.ws_stride;
 }
@@ -126,6 +128,7 @@ int qp_default_opts(qp_opts *o) {
   o->delta_reg = 0.f;
   o->refine_steps = 0;
   o->block = 0;
+  o->assembly = QPX_ASM_AUTO;
   return QPX_OK;
 }
 

@@ -37,6 +37,7 @@ struct Params {
   int32_t *rstatus, *riters;
   // options
   int32_t form, max_iter, pc, kb, relax_max_iter, refine;
+  int32_t asm_mode;  // H-block assembly: 0 FP32 VALU, 1 BF16x3 MFMA, 2 FP32 MFMA
   float tol, sigma, kappa_relax, relax_tol, delta_reg;
   // factor storage in global memory (when it does not fit LDS)
   float *ws;
@@ -51,7 +52,8 @@ struct Params {
 // server's arena; `state` holds x, y, z, s contiguously.
 struct SlotDesc {
   int32_t n, m, p, kb;      // sizes; kb = cap on bordered inequality rows
-  int32_t flags, pad_[3];   // flags: bit0 = fresh (run the initialisation)
+  int32_t flags, pad_[3];   // flags: bit0 = fresh (run the initialisation),
+                            // bits 1-2 = H-block assembly mode (Params::asm_mode)
   const float *Q, *q, *A, *b, *G, *h;
   float *state;             // x[n] y[p] z[m] s[m]
   float *ws;                // factor storage (global) or NULL
@@ -64,6 +66,8 @@ struct SlotDesc {
 size_t lds_bytes(int n, int m, int p, int kb, bool m_in_lds, int threads);
 // Floats of global factor storage per QP when M is not in LDS.
 int64_t ws_floats(int n, int m, int p, int kb);
+// Whether the matrix-core assembly's LDS staging fits the per-QP layout.
+bool mfma_stage_fits(int n, int m, int p, int kb, bool m_in_lds, int threads);
 // Largest dynamic LDS per block the kernels may use on this device.
 size_t lds_limit();
 
@@ -72,7 +76,8 @@ size_t lds_limit();
 hipError_t launch(const Params &P, int threads, bool m_in_lds, size_t lds,
                   int grid, hipStream_t stream);
 
-constexpr int kMaxN = 512;  // bordered system dimension supported by the kernels
+constexpr int kMaxN = 1024;  // bordered system dimension supported by the kernels
+// (above 512 rows only with 512 threads per QP: 16 rows per lane in the solves)
 
 // Launch configuration of one problem size: border cap, threads per QP,
 // whether the factor fits LDS, dynamic LDS bytes, global factor floats.
@@ -82,6 +87,7 @@ struct Plan {
   bool m_in_lds = true;
   size_t lds = 0;
   int64_t ws_stride = 0;
+  int amode = 0;  // resolved H-block assembly (Params::asm_mode)
 };
 
 inline int make_plan(int n, int m, int p, const qp_opts &o, Plan *pl) {
@@ -97,6 +103,7 @@ inline int make_plan(int n, int m, int p, const qp_opts &o, Plan *pl) {
   int T = o.block;
   if (T == 0) T = N <= 64 ? 128 : (N <= 256 ? 256 : 512);
   if (T != 128 && T != 256 && T != 512) return QPX_ERR_ARG;
+  if (N > 512 && T != 512) return QPX_ERR_UNSUPPORTED;
   pl->threads = T;
   const size_t lim = qpk::lds_limit();
   const size_t with_m = qpk::lds_bytes(n, m, p, kb, true, T);
@@ -110,6 +117,13 @@ inline int make_plan(int n, int m, int p, const qp_opts &o, Plan *pl) {
     if (pl->lds > lim) return QPX_ERR_UNSUPPORTED;
     pl->ws_stride = qpk::ws_floats(n, m, p, kb);
   }
+  const bool fits = qpk::mfma_stage_fits(n, m, p, kb, pl->m_in_lds, T);
+  int am = o.assembly;
+  if (am == QPX_ASM_AUTO)
+    am = (o.form == QPX_BOUNDED && n >= 128 && fits) ? QPX_ASM_BF16X3 : QPX_ASM_FP32;
+  else if (am != QPX_ASM_FP32 && !fits)
+    return QPX_ERR_UNSUPPORTED;
+  pl->amode = am == QPX_ASM_BF16X3 ? 1 : (am == QPX_ASM_MFMA_FP32 ? 2 : 0);
   return QPX_OK;
 }
 

@@ -190,8 +190,9 @@ struct Layout {
   int part, red;
   int w0, w1, rr, dd;  // rhs copies / residual for refinement; FP64 scratch
   int pan;             // (unused)
-  int zrow;            // a row of kNB zeros
   int role, bidx, elist, iflag;
+  int stg, stg_len;  // assembly staging: the span u0 .. end of dd, which
+                     // holds nothing live while the matrix is assembled
   int M;      // offset of M if in LDS, else -1
   int total;  // floats
 };
@@ -219,9 +220,12 @@ __host__ __device__ inline Layout make_layout(int n, int m, int p, int kb, bool 
   L.w0 = L.t0; L.w1 = L.t1; L.rr = take(L.Nmax);
   L.dd = take(2 * (2 * m + p + n + 8));
   L.pan = take(4);
-  L.zrow = take(kNB);  // 16 zeros for the triangular solves
   L.role = take(m); L.bidx = take(m); L.elist = take(m); L.iflag = take(16);
-  if (m_lds) { L.M = o; o += al4(moff(L.Nmax) + 16); } else { L.M = -1; }
+  L.stg = L.u0;
+  L.stg_len = L.pan - L.u0;
+  // M's storage ends with 16 floats past the last row: a zero row for the
+  // triangular solves, in M's own address space
+  if (m_lds) { L.M = o; o += al4(moff(L.Nmax) + kNB); } else { L.M = -1; }
   L.total = o;
   return L;
 }
@@ -307,161 +311,271 @@ QPD void coldot(const RF *R, int ld, int rows, int cols, const lf *const (&x)[NV
 // (M[j][i] = L[i][j]) so both triangular solves walk contiguous rows.
 // Returns false (uniformly) if a pivot sg_j * a_jj is not a positive
 // finite number.  RPL = rows per lane, >= ceil(N / 64).
-template <int T, int RPL, class MF>
-__device__ __noinline__ bool signed_cholesky(MF *M, int N, int npos, li *flag) {
-  M = rflp(M); N = rfl(N); npos = rfl(npos); flag = rflp(flag);
-  typedef typename Vec4<MF>::type V4;
+// One 4x4 tile of the rank-16 update M[i][j] -= sum_c L[i][p0+c] sg L[j][p0+c]
+// for i in [i0, i0+4), j in [j0, j0+4), j <= i, with the panel starting at
+// column p0 (16-byte row-segment loads).
+template <class MF>
+QPD void rank16_tile(MF *M, int N, int npos, int p0, int i0, int j0) {
   typedef typename Vec4<const MF>::type CV4;
+  int oi[4], oj[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    oi[a] = moff(min(i0 + a, N - 1));
+    oj[a] = moff(min(j0 + a, N - 1));
+  }
+  float acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int bq = 0; bq < 4; ++bq) acc[a][bq] = 0.f;
+#pragma unroll 1
+  for (int c = 0; c < kNB; c += 4) {
+    f4v av[4], bv[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      av[a] = *reinterpret_cast<CV4 *>(M + oi[a] + p0 + c);
+      bv[a] = *reinterpret_cast<CV4 *>(M + oj[a] + p0 + c);
+    }
+    const float s0 = (p0 + c + 0) < npos ? 1.f : -1.f;
+    const float s1 = (p0 + c + 1) < npos ? 1.f : -1.f;
+    const float s2 = (p0 + c + 2) < npos ? 1.f : -1.f;
+    const float s3 = (p0 + c + 3) < npos ? 1.f : -1.f;
+#pragma unroll
+    for (int bq = 0; bq < 4; ++bq) {
+      bv[bq].x *= s0; bv[bq].y *= s1; bv[bq].z *= s2; bv[bq].w *= s3;
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int bq = 0; bq < 4; ++bq) {
+        float r = acc[a][bq];
+        r = fmaf(av[a].x, bv[bq].x, r);
+        r = fmaf(av[a].y, bv[bq].y, r);
+        r = fmaf(av[a].z, bv[bq].z, r);
+        r = fmaf(av[a].w, bv[bq].w, r);
+        acc[a][bq] = r;
+      }
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int i = i0 + a;
+    if (i < N) {
+#pragma unroll
+      for (int bq = 0; bq < 4; ++bq) {
+        const int j = j0 + bq;
+        if (j <= i) M[oi[a] + j] -= acc[a][bq];
+      }
+    }
+  }
+}
+
+// One row's 16-column panel segment M[i][k0 .. k0+15] into registers (zeros
+// for rows at or beyond N), and back with exact zeros right of the diagonal
+// (r = i - k0 is the row's position in the panel).
+template <class MF>
+QPD void panel_load(const MF *M, int N, int k0, int i, float (&R)[kNB]) {
+  typedef typename Vec4<const MF>::type CV4;
+  const bool in = i < N;
+  const MF *row = M + moff(min(i, N - 1)) + k0;
+#pragma unroll
+  for (int c = 0; c < kNB; c += 4) {
+    const f4v v4 = *reinterpret_cast<CV4 *>(row + c);
+    R[c] = in ? v4.x : 0.f;
+    R[c + 1] = in ? v4.y : 0.f;
+    R[c + 2] = in ? v4.z : 0.f;
+    R[c + 3] = in ? v4.w : 0.f;
+  }
+}
+template <class MF>
+QPD void panel_store(MF *M, int N, int k0, int i, const float (&R)[kNB]) {
+  typedef typename Vec4<MF>::type V4;
+  if (i >= N) return;
+  const int r = i - k0;
+  MF *row = M + moff(i) + k0;
+#pragma unroll
+  for (int c = 0; c < kNB; c += 4) {
+    f4v v4;
+    v4.x = (c + 0 <= r) ? R[c + 0] : 0.f;
+    v4.y = (c + 1 <= r) ? R[c + 1] : 0.f;
+    v4.z = (c + 2 <= r) ? R[c + 2] : 0.f;
+    v4.w = (c + 3 <= r) ? R[c + 3] : 0.f;
+    *reinterpret_cast<V4 *>(row + c) = v4;
+  }
+}
+
+// Factor the 16-column panel starting at k0 (rows k0..N-1) by one wave in
+// registers (lane = row, readlane broadcasts); writes L back with exact
+// zeros right of the diagonal.  Rows are taken 64 at a time: chunk 0 holds
+// the diagonal block, and up to four more chunks are eliminated in the same
+// sweep; any further chunks (more than 320 rows) replay the eliminations
+// with the finished diagonal block, so registers stay bounded for any N.
+// Returns true if a pivot failed.
+//
+// Dynamic regularisation (dyn): a pivot sg*a_jj that is not above
+// kPivTol * pmax, with pmax the largest pivot accepted so far, is taken as
+// numerically zero (or of the wrong sign through rounding) and replaced by
+// kPivReg * pmax; nreg counts the replacements.  The factor is then that of
+// M plus a small diagonal, and callers refine against the exact operator.
+// This keeps a degenerate system (dependent border rows, e.g. more active
+// rows plus equalities than unknowns) factorable in FP32.
+constexpr float kPivTol = 1e-6f;
+constexpr float kPivReg = 1e-5f;
+template <int RPL, class MF>
+QPD bool factor_panel(MF *M, int N, int npos, int k0, bool dyn, float &pmax, int &nreg) {
+  constexpr int GRP = RPL - 1 < 4 ? RPL - 1 : 4;
+  const int lane = threadIdx.x & 63;
+  const int kb = min(kNB, N - k0);
+  float P0[kNB], P[GRP > 0 ? GRP : 1][kNB], iv[kNB];
+  panel_load(M, N, k0, k0 + lane, P0);
+#pragma unroll
+  for (int g = 0; g < GRP; ++g) panel_load(M, N, k0, k0 + lane + 64 * (1 + g), P[g]);
+  bool fail = false;
+#pragma unroll
+  for (int jj = 0; jj < kNB; ++jj) {
+    iv[jj] = 0.f;
+    if (jj < kb) {
+      // row k0+jj is in lane jj of chunk 0
+      const float sg = (k0 + jj) < npos ? 1.f : -1.f;
+      float tt = sg * readlane(P0[jj], jj);
+      if (dyn && !(tt > kPivTol * pmax) && tt >= -FLT_MAX && pmax > 0.f) {
+        tt = kPivReg * pmax;
+        ++nreg;
+      }
+      const bool ok = tt > 0.f && tt <= FLT_MAX;
+      if (ok) pmax = fmaxf(pmax, tt);
+      fail |= !ok;
+      const float d = ok ? sqrtf(tt) : 1.f;
+      const float inv = sg / d;
+      iv[jj] = inv;
+      P0[jj] = lane > jj ? P0[jj] * inv : (lane == jj ? d : P0[jj]);
+#pragma unroll
+      for (int g = 0; g < GRP; ++g) P[g][jj] *= inv;
+#pragma unroll
+      for (int cc = jj + 1; cc < kNB; ++cc) {
+        const float lc = readlane(P0[jj], cc) * sg;  // L[k0+cc][k0+jj] sg
+        P0[cc] = fmaf(-P0[jj], lc, P0[cc]);
+#pragma unroll
+        for (int g = 0; g < GRP; ++g) P[g][cc] = fmaf(-P[g][jj], lc, P[g][cc]);
+      }
+    }
+  }
+  panel_store(M, N, k0, k0 + lane, P0);
+#pragma unroll
+  for (int g = 0; g < GRP; ++g) panel_store(M, N, k0, k0 + lane + 64 * (1 + g), P[g]);
+#pragma unroll 1
+  for (int t0 = 1 + GRP; t0 < RPL; t0 += GRP) {
+    if (k0 + 64 * t0 >= N) break;
+#pragma unroll
+    for (int g = 0; g < GRP; ++g) panel_load(M, N, k0, k0 + lane + 64 * (t0 + g), P[g]);
+#pragma unroll
+    for (int jj = 0; jj < kNB; ++jj) {
+      if (jj < kb) {
+        const float sg = (k0 + jj) < npos ? 1.f : -1.f;
+#pragma unroll
+        for (int g = 0; g < GRP; ++g) P[g][jj] *= iv[jj];
+#pragma unroll
+        for (int cc = jj + 1; cc < kNB; ++cc) {
+          const float lc = readlane(P0[jj], cc) * sg;
+#pragma unroll
+          for (int g = 0; g < GRP; ++g) P[g][cc] = fmaf(-P[g][jj], lc, P[g][cc]);
+        }
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < GRP; ++g) panel_store(M, N, k0, k0 + lane + 64 * (t0 + g), P[g]);
+  }
+  return fail;
+}
+
+// In-place M = L diag(sg) L' (lower triangle, packed-blocked layout),
+// sg_j = +1 for j < npos, -1 otherwise.  Blocked right-looking with one
+// panel of lookahead: after panel k is factored, all waves first apply it
+// to the next panel's 16 columns; then wave 0 factors the next panel while
+// the other waves apply panel k to the rest of the trailing matrix.  The
+// strict upper part of each row's last 16-column segment is left at exact
+// zeros.  Returns false (uniformly) if a pivot sg_j * a_jj is not a positive
+// finite number.  With dyn, numerically zero pivots are regularised (see
+// factor_panel) and flag[2] receives their count.  flag[0] is the failure
+// flag; flag[1] is left alone.  RPL = rows per lane, >= ceil(N / 64).
+template <int T, int RPL, class MF>
+__device__ __noinline__ bool signed_cholesky(MF *M, int N, int npos, li *flag, bool dyn) {
+  M = rflp(M); N = rfl(N); npos = rfl(npos); flag = rflp(flag); dyn = rfl(dyn);
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  if (tid == 0) *flag = 0;
+  // wave 0's running pivot scale and count of regularised pivots
+  float pmax = 0.f;
+  int nreg = 0;
+  if (tid == 0) { flag[0] = 0; flag[2] = 0; }
+  if (wid == 0) {
+    const bool fail = factor_panel<RPL>(M, N, npos, 0, dyn, pmax, nreg);
+    if (fail && lane == 0) flag[0] = 1;
+  }
   __syncthreads();
 #pragma unroll 1
-  for (int k0 = 0; k0 < N; k0 += kNB) {
-    const int kb = min(kNB, N - k0);
-    if (wid == 0) {
-      // panel rows k0 + lane + 64 t, columns k0 .. k0+15, held in registers
-      float P[RPL][kNB];
-#pragma unroll
-      for (int t = 0; t < RPL; ++t) {
-        const int i = k0 + lane + 64 * t;
-        const bool in = i < N;
-        const MF *row = M + moff(min(i, N - 1)) + k0;
-#pragma unroll
-        for (int c = 0; c < kNB; c += 4) {
-          const f4v v4 = *reinterpret_cast<CV4 *>(row + c);
-          P[t][c] = in ? v4.x : 0.f;
-          P[t][c + 1] = in ? v4.y : 0.f;
-          P[t][c + 2] = in ? v4.z : 0.f;
-          P[t][c + 3] = in ? v4.w : 0.f;
+  for (int k0 = 0; k0 + kNB < N; k0 += kNB) {
+    const int r0 = k0 + kNB, R = N - r0;
+    // (1) apply panel k0 to the next panel's columns [r0, r0+16)
+    {
+      const int ntr = (R + 3) >> 2;                       // tile rows
+      const int nla = ntr <= 4 ? ntr * (ntr + 1) / 2 : 10 + 4 * (ntr - 4);
+      for (int t = tid; t < nla; t += T) {
+        int ti, tj;
+        if (t < 10) {
+          ti = (int)((sqrtf(8.f * (float)t + 1.f) - 1.f) * 0.5f);
+          while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+          while (ti * (ti + 1) / 2 > t) --ti;
+          tj = t - ti * (ti + 1) / 2;
+        } else {
+          ti = 4 + (t - 10) / 4;
+          tj = (t - 10) & 3;
         }
+        rank16_tile(M, N, npos, k0, r0 + 4 * ti, r0 + 4 * tj);
       }
-      bool fail = false;
-#pragma unroll
-      for (int jj = 0; jj < kNB; ++jj) {
-        if (jj < kb) {
-          // row k0+jj is in lane jj, slot 0
-          const float sg = (k0 + jj) < npos ? 1.f : -1.f;
-          const float tt = sg * readlane(P[0][jj], jj);
-          const bool ok = tt > 0.f && tt <= FLT_MAX;
-          fail |= !ok;
-          const float d = ok ? sqrtf(tt) : 1.f;
-          const float inv = sg / d;
-#pragma unroll
-          for (int t = 0; t < RPL; ++t) {
-            const int r = lane + 64 * t;
-            P[t][jj] = r > jj ? P[t][jj] * inv : (r == jj ? d : P[t][jj]);
-          }
-#pragma unroll
-          for (int cc = jj + 1; cc < kNB; ++cc) {
-            const float lc = readlane(P[0][jj], cc) * sg;  // L[k0+cc][k0+jj] sg
-#pragma unroll
-            for (int t = 0; t < RPL; ++t) P[t][cc] = fmaf(-P[t][jj], lc, P[t][cc]);
-          }
-        }
-      }
-      // write back whole 16-column segments; entries right of the diagonal
-      // (the row's padding inside the diagonal block) are set to exact zeros,
-      // which the triangular solves rely on
-#pragma unroll
-      for (int t = 0; t < RPL; ++t) {
-        const int r = lane + 64 * t, i = k0 + r;
-        if (i < N) {
-          MF *row = M + moff(i) + k0;
-#pragma unroll
-          for (int c = 0; c < kNB; c += 4) {
-            f4v v4;
-            v4.x = (c + 0 <= r) ? P[t][c + 0] : 0.f;
-            v4.y = (c + 1 <= r) ? P[t][c + 1] : 0.f;
-            v4.z = (c + 2 <= r) ? P[t][c + 2] : 0.f;
-            v4.w = (c + 3 <= r) ? P[t][c + 3] : 0.f;
-            *reinterpret_cast<V4 *>(row + c) = v4;
-          }
-        }
-      }
-      if (fail && lane == 0) *flag = 1;
     }
     __syncthreads();
-    // trailing update of rows/cols [r0, N): M -= Lp diag(sg_p) Lp'
-    const int r0 = k0 + kb, R = N - r0;
-    if (R > 0) {
-      const int nt = (R + 3) >> 2;
-      const int ntiles = nt * (nt + 1) / 2;
-      for (int t = tid; t < ntiles; t += T) {
-        int ti = (int)((sqrtf(8.f * (float)t + 1.f) - 1.f) * 0.5f);
-        while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
-        while (ti * (ti + 1) / 2 > t) --ti;
-        const int tj = t - ti * (ti + 1) / 2;
-        const int i0 = r0 + 4 * ti, j0 = r0 + 4 * tj;
-        int oi[4], oj[4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-          oi[a] = moff(min(i0 + a, N - 1));
-          oj[a] = moff(min(j0 + a, N - 1));
-        }
-        float acc[4][4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int bq = 0; bq < 4; ++bq) acc[a][bq] = 0.f;
-#pragma unroll 1
-        for (int c = 0; c < kNB; c += 4) {
-          f4v av[4], bv[4];
-#pragma unroll
-          for (int a = 0; a < 4; ++a) {
-            av[a] = *reinterpret_cast<CV4 *>(M + oi[a] + k0 + c);
-            bv[a] = *reinterpret_cast<CV4 *>(M + oj[a] + k0 + c);
-          }
-          const float s0 = (k0 + c + 0) < npos ? 1.f : -1.f;
-          const float s1 = (k0 + c + 1) < npos ? 1.f : -1.f;
-          const float s2 = (k0 + c + 2) < npos ? 1.f : -1.f;
-          const float s3 = (k0 + c + 3) < npos ? 1.f : -1.f;
-#pragma unroll
-          for (int bq = 0; bq < 4; ++bq) {
-            bv[bq].x *= s0; bv[bq].y *= s1; bv[bq].z *= s2; bv[bq].w *= s3;
-          }
-#pragma unroll
-          for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int bq = 0; bq < 4; ++bq) {
-              float r = acc[a][bq];
-              r = fmaf(av[a].x, bv[bq].x, r);
-              r = fmaf(av[a].y, bv[bq].y, r);
-              r = fmaf(av[a].z, bv[bq].z, r);
-              r = fmaf(av[a].w, bv[bq].w, r);
-              acc[a][bq] = r;
-            }
-        }
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-          const int i = i0 + a;
-          if (i < N) {
-#pragma unroll
-            for (int bq = 0; bq < 4; ++bq) {
-              const int j = j0 + bq;
-              if (j <= i) M[oi[a] + j] -= acc[a][bq];
-            }
-          }
+    // (2) wave 0: factor the next panel; waves 1..: rest of the update
+    if (wid == 0) {
+      const bool fail = factor_panel<RPL>(M, N, npos, r0, dyn, pmax, nreg);
+      if (fail && lane == 0) flag[0] = 1;
+    } else {
+      const int r1 = r0 + kNB, R1 = N - r1;
+      if (R1 > 0) {
+        const int nt = (R1 + 3) >> 2;
+        const int ntiles = nt * (nt + 1) / 2;
+        for (int t = tid - 64; t < ntiles; t += T - 64) {
+          int ti = (int)((sqrtf(8.f * (float)t + 1.f) - 1.f) * 0.5f);
+          while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+          while (ti * (ti + 1) / 2 > t) --ti;
+          const int tj = t - ti * (ti + 1) / 2;
+          rank16_tile(M, N, npos, k0, r1 + 4 * ti, r1 + 4 * tj);
         }
       }
     }
     __syncthreads();
   }
-  return *flag == 0;
+  if (tid == 0) flag[2] = nreg;
+  __syncthreads();
+  return flag[0] == 0;
 }
 
 // Solve (L diag(sg) L') u = r in place for one right-hand side held in
 // `r` (length N), by a single wave with the vector in registers (lane owns
-// rows lane + 64 t).  Uses the L' copy in the strict upper triangle for the
-// forward sweep and L's rows for the backward sweep; dinv[j] = 1 / L[j][j].
+// rows RPL*lane + t).  The forward sweep walks rows of L, the backward sweep
+// reads L[j][i] from row j; dinv[j] = 1 / L[j][j].  Each 16-column block of L
+// is loaded into registers in bursts of CW columns (all 16, or two halves
+// of 8 when RPL = 16 to bound registers), then its dependent steps run
+// register-only.
 template <int RPL, class MF>
-QPD void signed_solve_wave(const MF *M, int N, int npos, const lf *dinv, lf *r, const lf *zrow) {
+QPD void signed_solve_wave(const MF *M, int N, int npos, const lf *dinv, lf *r, const MF *zrow) {
   typedef typename Vec4<const MF>::type CV4;
   static_assert(kNB % RPL == 0, "row slot must be static within a block");
+  constexpr int CW = RPL > 8 ? 8 : kNB;
   const int lane = threadIdx.x & 63;
   // lane l owns rows RPL*l + t, so row j sits in lane j/RPL, slot j%RPL.
   // The factor holds exact zeros right of the diagonal inside every row's
   // padded 16-column segment; rows that must not be touched in a block read
-  // the zero row `zrow` instead, so no per-step masking is needed.  The
+  // the zero row `zrow` (16 zeros stored after M's last row, so both
+  // pointers are in M's address space) instead, so no per-step masking is
+  // needed.  The
   // diagonal entry is applied by overwriting the owner's value after the FMA.
   float a[RPL];
 #pragma unroll
@@ -472,30 +586,33 @@ QPD void signed_solve_wave(const MF *M, int N, int npos, const lf *dinv, lf *r, 
   // forward sweep L w = r: w_j = a_j / L[j][j], then a_i -= L[i][j] w_j, i > j
 #pragma unroll 1
   for (int j0 = 0; j0 < N; j0 += kNB) {
-    float Lc[RPL][kNB], dv[kNB];
 #pragma unroll
-    for (int t = 0; t < RPL; ++t) {
-      const int i = RPL * lane + t;
-      const bool in = i >= j0 && i < N;
-      // rows below the block: L[i][j0..j0+15]; rows in the block: their
-      // lower part with zeros right of the diagonal; finished rows: zeros
-      const MF *row = in ? M + moff(i) + j0 : (const MF *)zrow;
+    for (int h = 0; h < kNB; h += CW) {
+      float Lc[RPL][CW], dv[CW];
 #pragma unroll
-      for (int c = 0; c < kNB; c += 4) {
-        const f4v v4 = *reinterpret_cast<CV4 *>(row + c);
-        Lc[t][c] = v4.x; Lc[t][c + 1] = v4.y; Lc[t][c + 2] = v4.z; Lc[t][c + 3] = v4.w;
+      for (int t = 0; t < RPL; ++t) {
+        const int i = RPL * lane + t;
+        const bool in = i >= j0 && i < N;
+        // rows below the block: L[i][j0..j0+15]; rows in the block: their
+        // lower part with zeros right of the diagonal; finished rows: zeros
+        const MF *row = in ? M + moff(i) + j0 + h : zrow + h;
+#pragma unroll
+        for (int c = 0; c < CW; c += 4) {
+          const f4v v4 = *reinterpret_cast<CV4 *>(row + c);
+          Lc[t][c] = v4.x; Lc[t][c + 1] = v4.y; Lc[t][c + 2] = v4.z; Lc[t][c + 3] = v4.w;
+        }
       }
-    }
 #pragma unroll
-    for (int c = 0; c < kNB; ++c) dv[c] = dinv[min(j0 + c, N - 1)];
+      for (int c = 0; c < CW; ++c) dv[c] = dinv[min(j0 + h + c, N - 1)];
 #pragma unroll
-    for (int c = 0; c < kNB; ++c) {
-      const int j = j0 + c;
-      if (j < N) {
-        const float wj = readlane(a[c % RPL], j / RPL) * dv[c];
+      for (int c = 0; c < CW; ++c) {
+        const int j = j0 + h + c;
+        if (j < N) {
+          const float wj = readlane(a[(h + c) % RPL], j / RPL) * dv[c];
 #pragma unroll
-        for (int t = 0; t < RPL; ++t) a[t] = fmaf(-Lc[t][c], wj, a[t]);
-        if (lane == j / RPL) a[c % RPL] = wj;
+          for (int t = 0; t < RPL; ++t) a[t] = fmaf(-Lc[t][c], wj, a[t]);
+          if (lane == j / RPL) a[(h + c) % RPL] = wj;
+        }
       }
     }
   }
@@ -508,28 +625,31 @@ QPD void signed_solve_wave(const MF *M, int N, int npos, const lf *dinv, lf *r, 
   // backward sweep L' u = w: u_j = a_j / L[j][j], then a_i -= L[j][i] u_j, i < j
 #pragma unroll 1
   for (int b0 = ((N - 1) / kNB) * kNB; b0 >= 0; b0 -= kNB) {
-    float Lr[RPL][kNB], dv[kNB];
 #pragma unroll
-    for (int c = 0; c < kNB; ++c) {
-      const int j = min(b0 + c, N - 1);
-      const MF *row = M + moff(j);
+    for (int h = kNB - CW; h >= 0; h -= CW) {
+      float Lr[RPL][CW], dv[CW];
 #pragma unroll
-      for (int t = 0; t < RPL; ++t) {
-        const int i = RPL * lane + t;
-        // rows above the block read row j; rows in the block read row j's
-        // zero padding right of its diagonal; rows below read zeros
-        Lr[t][c] = i < b0 + kNB ? row[i] : zrow[c];
+      for (int c = 0; c < CW; ++c) {
+        const int j = min(b0 + h + c, N - 1);
+        const MF *row = M + moff(j);
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) {
+          const int i = RPL * lane + t;
+          // rows above the block read row j; rows in the block read row j's
+          // zero padding right of its diagonal; rows below read zeros
+          Lr[t][c] = i < b0 + kNB ? row[i] : 0.f;
+        }
+        dv[c] = dinv[j];
       }
-      dv[c] = dinv[j];
-    }
 #pragma unroll
-    for (int c = kNB - 1; c >= 0; --c) {
-      const int j = b0 + c;
-      if (j < N) {
-        const float uj = readlane(a[c % RPL], j / RPL) * dv[c];
+      for (int c = CW - 1; c >= 0; --c) {
+        const int j = b0 + h + c;
+        if (j < N) {
+          const float uj = readlane(a[(h + c) % RPL], j / RPL) * dv[c];
 #pragma unroll
-        for (int t = 0; t < RPL; ++t) a[t] = fmaf(-Lr[t][c], uj, a[t]);
-        if (lane == j / RPL) a[c % RPL] = uj;
+          for (int t = 0; t < RPL; ++t) a[t] = fmaf(-Lr[t][c], uj, a[t]);
+          if (lane == j / RPL) a[(h + c) % RPL] = uj;
+        }
       }
     }
   }
@@ -605,9 +725,12 @@ struct Ctx {
   lf *tGz, *tAy;
   lf *t0, *t1, *u0, *u1, *dv0, *dv1, *dinv;
   lf *part, *red;
-  lf *w0, *w1, *rr, *pan, *zrow;
+  lf *w0, *w1, *rr, *pan;
+  MF *mz;    // 16 zeros after M's last row (same address space as M)
   ldd *dd;
   li *role, *bidx, *elist, *iflag;
+  lf *stg;    // matrix-core assembly staging (aliases u0 .. dd)
+  int amode;  // H-block assembly: 0 FP32 VALU, 1 BF16x3 MFMA, 2 FP32 MFMA
   __attribute__((address_space(3))) long long *pt;
 };
 
@@ -625,12 +748,16 @@ QPD void init_ctx(Ctx<MF> &C, lf *sm, const Layout &L, MF *Mptr) {
   C.t0 = sm + L.t0; C.t1 = sm + L.t1; C.u0 = sm + L.u0; C.u1 = sm + L.u1;
   C.dv0 = sm + L.dv0; C.dv1 = sm + L.dv1; C.dinv = sm + L.dinv;
   C.part = sm + L.part; C.red = sm + L.red;
-  C.w0 = sm + L.w0; C.w1 = sm + L.w1; C.rr = sm + L.rr; C.pan = sm + L.pan; C.zrow = sm + L.zrow;
+  C.w0 = sm + L.w0; C.w1 = sm + L.w1; C.rr = sm + L.rr; C.pan = sm + L.pan;
+  C.mz = Mptr + moff(L.Nmax);
   C.dd = reinterpret_cast<ldd *>(sm + L.dd);
   C.role = reinterpret_cast<li *>(sm + L.role);
   C.bidx = reinterpret_cast<li *>(sm + L.bidx);
   C.elist = reinterpret_cast<li *>(sm + L.elist);
   C.iflag = reinterpret_cast<li *>(sm + L.iflag);
+  C.stg = sm + L.stg;
+  C.amode = 0;
+  C.pt = nullptr;  // set by profiling builds
 }
 
 
@@ -651,9 +778,10 @@ QPD Ctx<MF> uctx(const Ctx<MF> &I) {
   C.t0 = rflp(I.t0); C.t1 = rflp(I.t1); C.u0 = rflp(I.u0); C.u1 = rflp(I.u1);
   C.dv0 = rflp(I.dv0); C.dv1 = rflp(I.dv1); C.dinv = rflp(I.dinv);
   C.part = rflp(I.part); C.red = rflp(I.red);
-  C.w0 = rflp(I.w0); C.w1 = rflp(I.w1); C.rr = rflp(I.rr); C.pan = rflp(I.pan); C.zrow = rflp(I.zrow);
+  C.w0 = rflp(I.w0); C.w1 = rflp(I.w1); C.rr = rflp(I.rr); C.pan = rflp(I.pan); C.mz = rflp(I.mz);
   C.dd = rflp(I.dd);
   C.role = rflp(I.role); C.bidx = rflp(I.bidx); C.elist = rflp(I.elist); C.iflag = rflp(I.iflag);
+  C.stg = rflp(I.stg); C.amode = rfl(I.amode);
   C.pt = rflp(I.pt);
   return C;
 }
@@ -766,52 +894,216 @@ template <int T, class CT>
 __device__ __noinline__ int partition_bounded(CT &Cin_, float kappa) {
   CT C = uctx(Cin_);
   kappa = rflf(kappa);
-  const int m = C.m, tid = threadIdx.x;
-  li *cand = C.role;  // temporarily: candidate flags
-  float cnt[1] = {0.f};
-  for (int i = tid; i < m; i += T) {
-    const float vi = C.v[i];
-    const float r = sqrtf(fmaf(vi, vi, 4.f * kappa));
-    C.E[i] = dbk(vi, kappa, r);
-    C.D[i] = dbk(-vi, kappa, r);
-    C.c[i] = 1.f / r;
-    const int f = vi > 0.f;
-    cand[i] = f;
-    cnt[0] += (float)f;
+  const int m = C.m, kb = C.kb, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  constexpr int NW = T / 64;
+  li *ws = reinterpret_cast<li *>(C.red);  // per-wave counts [2][NW]
+  const unsigned long long below = (1ull << lane) - 1ull;
+  // One sweep: retraction derivatives, and the border / eliminated lists in
+  // row order from wave ballots (the common case: at most kb rows with v > 0)
+  int nb = 0, ne = 0;
+  for (int i0 = 0; i0 < m; i0 += T) {
+    const int i = i0 + tid;
+    const bool valid = i < m;
+    bool f = false;
+    if (valid) {
+      const float vi = C.v[i];
+      const float r = sqrtf(fmaf(vi, vi, 4.f * kappa));
+      C.E[i] = dbk(vi, kappa, r);
+      C.D[i] = dbk(-vi, kappa, r);
+      C.c[i] = 1.f / r;
+      f = vi > 0.f;
+    }
+    const unsigned long long bb = __ballot(valid && f), be = __ballot(valid && !f);
+    if (lane == 0) {
+      ws[w] = __popcll(bb);
+      ws[NW + w] = __popcll(be);
+    }
+    __syncthreads();
+    int ob = 0, oe = 0, tb = 0, te = 0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+      const int cb = ws[k], ce = ws[NW + k];
+      ob += k < w ? cb : 0;
+      oe += k < w ? ce : 0;
+      tb += cb;
+      te += ce;
+    }
+    if (valid) {
+      if (f) {
+        const int k = nb + ob + __popcll(bb & below);
+        if (k < kb) C.bidx[k] = i;
+        C.role[i] = k;
+      } else {
+        C.elist[ne + oe + __popcll(be & below)] = i;
+        C.role[i] = -1;
+      }
+    }
+    nb += tb;
+    ne += te;
+    __syncthreads();
   }
-  block_reduce<T, OpSum, 1>(cnt, C.red);
-  const int ncand = (int)cnt[0];
-  if (ncand > C.kb) {
-    // keep the kb largest v (ties by row index)
-    li *keep = C.elist;  // scratch flags
+  if (nb > kb) {
+    // more candidates than border slots: keep the kb largest v (ties by row
+    // index) and eliminate the rest
+    li *cand = C.role;
     for (int i = tid; i < m; i += T) {
       int f = 0;
-      if (cand[i]) {
-        const float vi = C.v[i];
+      const float vi = C.v[i];
+      if (vi > 0.f) {
         int rank = 0;
         for (int j = 0; j < m; ++j) {
           const float vj = C.v[j];
           rank += (vj > vi) || (vj == vi && j < i);
         }
-        f = rank < C.kb;
+        f = rank < kb;
       }
-      keep[i] = f;
+      cand[i] = f;
     }
     __syncthreads();
-    for (int i = tid; i < m; i += T) cand[i] = keep[i];
+    nb = compact_rows<T>(cand, m, C.bidx, C.red);
+    for (int i = tid; i < m; i += T) cand[i] = !cand[i];
+    __syncthreads();
+    ne = compact_rows<T>(cand, m, C.elist, C.red);
+    for (int i = tid; i < m; i += T) C.role[i] = -1;
+    __syncthreads();
+    for (int k = tid; k < nb; k += T) C.role[C.bidx[k]] = k;
   }
-  __syncthreads();
-  const int nb = compact_rows<T>(cand, m, C.bidx, C.red);
-  // eliminated rows = not bordered
-  for (int i = tid; i < m; i += T) cand[i] = !cand[i];
-  __syncthreads();
-  const int ne = compact_rows<T>(cand, m, C.elist, C.red);
-  for (int i = tid; i < m; i += T) C.role[i] = -1;
-  __syncthreads();
-  for (int k = tid; k < nb; k += T) C.role[C.bidx[k]] = k;
   if (tid == 0) C.iflag[1] = ne;
   __syncthreads();
   return nb;
+}
+
+// ---------------------------------------------------------------------------
+// H-block assembly on the matrix cores (used for large n).
+//
+// H = Q + Y'Y with Y = diag(sqrt(w)) G_I (rows of G in elist).  Y is staged
+// through LDS 16 rows at a time, column-major: column c of the chunk is a
+// record of kStgRec floats, so the MFMA fragment of a lane (4 consecutive
+// rows of one column) is a single 8- or 16-byte load, and the A operand of a
+// tile (Y_i') and its B operand (Y_j) come from the same records.  Each wave
+// owns up to kAsmTiles 16x16 tiles of the lower triangle per pass and
+// accumulates them over all chunks in FP32.
+//   amode 1 (BF16x3): y = hi + lo with hi = bf16(y), lo = bf16(y - hi);
+//     Y_i'Y_j ~ lo_i'hi_j + hi_i'lo_j + hi_i'hi_j (16x16x16 bf16 MFMA, FP32
+//     accumulation).  The dropped lo'lo term and the rounding of lo leave a
+//     relative error of about 2^-16 per product; the Newton and adjoint
+//     solves refine against the exact operator to recover FP32 accuracy.
+//   amode 2: FP32 inputs on the 16x16x4 FP32 MFMA.
+// Record layout: amode 1: hi of rows 0..15 as 16 bf16 (floats 0..7), lo as
+// 16 bf16 (floats 8..15); amode 2: rows 0..15 as floats 0..15.  Floats
+// 16..19 pad the record to 80 bytes, which spreads the 16 columns a
+// fragment load touches over the LDS banks.
+constexpr int kStgRec = 20;
+constexpr int kAsmTiles = 9;
+typedef short s4v __attribute__((ext_vector_type(4)));
+typedef unsigned u2v __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(3))) u2v lu2;
+typedef __attribute__((address_space(3))) unsigned lu;
+
+QPD unsigned bf16_pair(float a, float b) {
+  return (unsigned)__builtin_bit_cast(unsigned short, (__bf16)a) |
+         ((unsigned)__builtin_bit_cast(unsigned short, (__bf16)b) << 16);
+}
+
+// LDS floats the matrix-core assembly stages for n columns.
+__host__ __device__ inline int stage_floats(int n) { return ((n + 15) & ~15) * kStgRec; }
+
+// Lower-triangular tile t -> (ti, tj), tj <= ti, in row order.
+QPD void tile_ij(int t, int &ti, int &tj) {
+  int i = (int)((sqrtf(8.f * (float)t + 1.f) - 1.f) * 0.5f);
+  while ((i + 1) * (i + 2) / 2 <= t) ++i;
+  while (i * (i + 1) / 2 > t) --i;
+  ti = i;
+  tj = t - i * (i + 1) / 2;
+}
+
+template <int T, class CT>
+QPD void assemble_h_mfma(CT &C, int ne, const lf *wts) {
+  constexpr int W = T / 64;
+  const int n = C.n, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int n16 = (n + 15) & ~15, nt = n16 >> 4;
+  const int ntl = nt * (nt + 1) / 2;
+  const int passes = (ntl + W * kAsmTiles - 1) / (W * kAsmTiles);
+  const int tpw = (ntl + passes * W - 1) / (passes * W);
+  const bool bf = C.amode == 1;
+  const int g = lane >> 4, c16 = lane & 15;
+  lf *stg = C.stg;
+  auto *M = C.M;
+  for (int pass = 0; pass < passes; ++pass) {
+    int ti[kAsmTiles], tj[kAsmTiles];
+    bool val[kAsmTiles];
+    f4v acc[kAsmTiles];
+#pragma unroll
+    for (int j = 0; j < kAsmTiles; ++j) {
+      const int t = (pass * W + wid) * tpw + j;
+      val[j] = j < tpw && t < ntl;
+      ti[j] = tj[j] = 0;
+      if (val[j]) tile_ij(t, ti[j], tj[j]);
+      acc[j] = f4v{0.f, 0.f, 0.f, 0.f};
+    }
+    for (int k0 = 0; k0 < ne; k0 += 16) {
+      __syncthreads();  // the previous chunk has been consumed
+      // stage rows k0 .. k0+15 of Y; item e covers rows 2kp, 2kp+1 of column c
+      for (int e = tid; e < 8 * n16; e += T) {
+        const int kp = e / n16, c = e - kp * n16;
+        float y0 = 0.f, y1 = 0.f;
+        const int k = k0 + 2 * kp;
+        if (c < n) {
+          if (k < ne) {
+            const int r = C.elist[k];
+            y0 = sqrtf(wts[r]) * C.G[(size_t)r * n + c];
+          }
+          if (k + 1 < ne) {
+            const int r = C.elist[k + 1];
+            y1 = sqrtf(wts[r]) * C.G[(size_t)r * n + c];
+          }
+        }
+        lf *rec = stg + c * kStgRec;
+        if (bf) {
+          const float h0 = (float)(__bf16)y0, h1 = (float)(__bf16)y1;
+          reinterpret_cast<lu *>(rec)[kp] = bf16_pair(y0, y1);
+          reinterpret_cast<lu *>(rec)[8 + kp] = bf16_pair(y0 - h0, y1 - h1);
+        } else {
+          rec[2 * kp] = y0;
+          rec[2 * kp + 1] = y1;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < kAsmTiles; ++j) {
+        if (!val[j]) continue;
+        const lf *ra = stg + (16 * ti[j] + c16) * kStgRec;
+        const lf *rb = stg + (16 * tj[j] + c16) * kStgRec;
+        if (bf) {
+          const s4v ah = __builtin_bit_cast(s4v, *reinterpret_cast<const lu2 *>(ra + 2 * g));
+          const s4v al = __builtin_bit_cast(s4v, *reinterpret_cast<const lu2 *>(ra + 8 + 2 * g));
+          const s4v bh = __builtin_bit_cast(s4v, *reinterpret_cast<const lu2 *>(rb + 2 * g));
+          const s4v bl = __builtin_bit_cast(s4v, *reinterpret_cast<const lu2 *>(rb + 8 + 2 * g));
+          acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc[j], 0, 0, 0);
+          acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc[j], 0, 0, 0);
+          acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc[j], 0, 0, 0);
+        } else {
+          const f4v a = *reinterpret_cast<const lf4 *>(ra + 4 * g);
+          const f4v b = *reinterpret_cast<const lf4 *>(rb + 4 * g);
+          acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, acc[j], 0, 0, 0);
+          acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, acc[j], 0, 0, 0);
+          acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b.z, acc[j], 0, 0, 0);
+          acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b.w, acc[j], 0, 0, 0);
+        }
+      }
+    }
+    // result layout: register r of lane l is row 4(l/16) + r, column l%16
+#pragma unroll
+    for (int j = 0; j < kAsmTiles; ++j) {
+      if (!val[j]) continue;
+      const int col = 16 * tj[j] + c16;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * ti[j] + 4 * g + r;
+        if (row < n && col <= row) M[moff(row) + col] = C.Q[(size_t)row * n + col] + acc[j][r];
+      }
+    }
+  }
 }
 
 // Assemble M = [[H, C'], [C, -Dl]] (lower triangle) for N = n + nb + p.
@@ -824,6 +1116,9 @@ __device__ __noinline__ void assemble(CT &Cin_, int nb, int ne, const lf *wts, b
   nb = rfl(nb); ne = rfl(ne); wts = rflp(wts); bounded = rfl(bounded); delta = rflf(delta);
   const int n = C.n, p = C.p, tid = threadIdx.x;
   auto *M = C.M;
+  if (C.amode != 0) {
+    assemble_h_mfma<T>(C, ne, wts);
+  } else {
   // H block in 4x4 tiles.  Rows of G_I are staged through LDS in chunks
   // (coalesced cooperative loads), then each tile thread reads its 4 + 4
   // entries per row as 16-byte LDS loads.  The staging area is the (not yet
@@ -839,23 +1134,15 @@ __device__ __noinline__ void assemble(CT &Cin_, int nb, int ne, const lf *wts, b
   const int R = max(1, cap / ldg);
   const int nt = (n + 3) >> 2;
   const int ntiles = nt * (nt + 1) / 2;
-  int i0 = 0, j0 = 0;
-  const bool tile = tid < ntiles;
-  if (tile) {
-    const int t = tid;
-    int ti = (int)((sqrtf(8.f * (float)t + 1.f) - 1.f) * 0.5f);
-    while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
-    while (ti * (ti + 1) / 2 > t) --ti;
-    const int tj = t - ti * (ti + 1) / 2;
-    i0 = 4 * ti;
-    j0 = 4 * tj;
-  }
-  // ntiles <= T for n <= 4 * floor(sqrt(2T)) (n <= 88 at T = 256); larger n
-  // loop over tile groups below
+  // tile threads are split into `groups` that take every groups-th staged
+  // row; group 0 writes Q + its sum, the others add theirs in a fixed order
+  const int groups = ntiles <= T ? min(4, T / ntiles) : 1;
   for (int tb = 0; tb < ntiles; tb += T) {
-    const int t = tb + tid;
-    const bool act = t < ntiles;
-    if (tb > 0 && act) {
+    const int t = tb + (tid % (groups > 1 ? ntiles : T));
+    const int g = groups > 1 ? tid / ntiles : 0;
+    const bool act = t < ntiles && g < groups;
+    int i0 = 0, j0 = 0;
+    if (act) {
       int ti = (int)((sqrtf(8.f * (float)t + 1.f) - 1.f) * 0.5f);
       while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
       while (ti * (ti + 1) / 2 > t) --ti;
@@ -869,7 +1156,7 @@ __device__ __noinline__ void assemble(CT &Cin_, int nb, int ne, const lf *wts, b
 #pragma unroll
       for (int bq = 0; bq < 4; ++bq) {
         const int i = min(i0 + a, n - 1), j = min(j0 + bq, n - 1);
-        acc[a][bq] = act ? C.Q[(size_t)i * n + j] : 0.f;
+        acc[a][bq] = (act && g == 0) ? C.Q[(size_t)i * n + j] : 0.f;
       }
     for (int k0 = 0; k0 < ne; k0 += R) {
       const int kr = min(R, ne - k0);
@@ -882,7 +1169,7 @@ __device__ __noinline__ void assemble(CT &Cin_, int nb, int ne, const lf *wts, b
       __syncthreads();
       if (act) {
 #pragma unroll 2
-        for (int r = 0; r < kr; ++r) {
+        for (int r = g; r < kr; r += groups) {
           const float w = wts[C.elist[k0 + r]];
           const f4v gi = *reinterpret_cast<const lf4 *>(stage + r * ldg + i0);
           const f4v gj = *reinterpret_cast<const lf4 *>(stage + r * ldg + j0) * w;
@@ -895,22 +1182,28 @@ __device__ __noinline__ void assemble(CT &Cin_, int nb, int ne, const lf *wts, b
         }
       }
     }
-    __syncthreads();  // the staging area may alias M's border rows
-    if (act) {
+    for (int gg = 0; gg < groups; ++gg) {
+      __syncthreads();  // staging area (may alias M's border rows) / previous group
+      if (act && g == gg) {
 #pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        const int i = i0 + a;
-        if (i < n) {
+        for (int a = 0; a < 4; ++a) {
+          const int i = i0 + a;
+          if (i < n) {
 #pragma unroll
-          for (int bq = 0; bq < 4; ++bq) {
-            const int j = j0 + bq;
-            if (j <= i) M[moff(i) + j] = acc[a][bq];
+            for (int bq = 0; bq < 4; ++bq) {
+              const int j = j0 + bq;
+              if (j <= i) {
+                if (gg == 0) M[moff(i) + j] = acc[a][bq];
+                else M[moff(i) + j] += acc[a][bq];
+              }
+            }
           }
         }
       }
     }
   }
-  (void)tile;
+  }
+  __syncthreads();
   // border rows: [C | -Dl (lower part)]
   const int K = nb + p;
   for (int e = tid; e < K * (n + K); e += T) {
@@ -953,11 +1246,11 @@ __device__ __noinline__ void solve2(CT &Cin_, int N, bool both) {
   N = rfl(N); both = rfl(both);
   const int wid = threadIdx.x >> 6;
   if constexpr (T >= 128) {
-    if (wid == 0) signed_solve_wave<RPL>(C.M, N, C.n, C.dinv, C.u0, C.zrow);
-    else if (wid == 1 && both) signed_solve_wave<RPL>(C.M, N, C.n, C.dinv, C.u1, C.zrow);
+    if (wid == 0) signed_solve_wave<RPL>(C.M, N, C.n, C.dinv, C.u0, C.mz);
+    else if (wid == 1 && both) signed_solve_wave<RPL>(C.M, N, C.n, C.dinv, C.u1, C.mz);
   } else {
-    signed_solve_wave<RPL>(C.M, N, C.n, C.dinv, C.u0, C.zrow);
-    if (both) signed_solve_wave<RPL>(C.M, N, C.n, C.dinv, C.u1, C.zrow);
+    signed_solve_wave<RPL>(C.M, N, C.n, C.dinv, C.u0, C.mz);
+    if (both) signed_solve_wave<RPL>(C.M, N, C.n, C.dinv, C.u1, C.mz);
   }
   __syncthreads();
 }
@@ -1000,7 +1293,7 @@ __device__ __noinline__ void refine(CT &Cin_, int nb, bool bounded, const lf *w,
     }
     for (int a = tid; a < p; a += T) r[n + nb + a] = (float)((double)w[n + nb + a] - ax[a]);
     __syncthreads();
-    if (threadIdx.x < 64) signed_solve_wave<RPL>(C.M, N, n, C.dinv, r, C.zrow);
+    if (threadIdx.x < 64) signed_solve_wave<RPL>(C.M, N, n, C.dinv, r, C.mz);
     __syncthreads();
     for (int j = tid; j < N; j += T) u[j] += r[j];
     __syncthreads();
@@ -1042,13 +1335,13 @@ QPD bool factor_bounded(CT &C, int nb, int ne, const lf *wts, float delta_rel, b
   assemble<T>(C, nb, ne, wts, true, 0.f);
   if (delta_rel > 0.f) border_delta<T>(C, nb, delta_rel);
   QPK_PT(C, PH_ASM);
-  bool ok = signed_cholesky<T, RPL>(C.M, N, C.n, C.iflag);
+  bool ok = signed_cholesky<T, RPL>(C.M, N, C.n, C.iflag, true);
   QPK_PT(C, PH_FACT);
-  *regularised = delta_rel > 0.f;
+  *regularised = delta_rel > 0.f || C.iflag[2] > 0;
   if (!ok) {
     assemble<T>(C, nb, ne, wts, true, 0.f);
     border_delta<T>(C, nb, fmaxf(delta_rel, 1e-6f));
-    ok = signed_cholesky<T, RPL>(C.M, N, C.n, C.iflag);
+    ok = signed_cholesky<T, RPL>(C.M, N, C.n, C.iflag, true);
     *regularised = true;
   }
   return ok;
@@ -1171,8 +1464,9 @@ QPD int mkstatus(int st, int stage) { return st | (stage << 8); }
 // Initialisation (CVXOPT convention): solve [[Q+G'G, A'], [A, 0]] [x; y] =
 // [-q + G'h; b], zt = Gx - h, s = -zt, z = zt, each shifted positive.
 template <int T, int RPL, class CT>
-__device__ __noinline__ bool initialize(CT &Cin_, double &work) {
+__device__ __noinline__ bool initialize(CT &Cin_, double &work, bool dyn) {
   CT C = uctx(Cin_);
+  dyn = rfl(dyn);
   const int n = C.n, m = C.m, p = C.p, tid = threadIdx.x;
   for (int i = tid; i < m; i += T) C.E[i] = 1.f;  // unit weights
   for (int i = tid; i < m; i += T) C.role[i] = 1;
@@ -1180,7 +1474,7 @@ __device__ __noinline__ bool initialize(CT &Cin_, double &work) {
   const int ne = compact_rows<T>(C.role, m, C.elist, C.red);
   assemble<T>(C, 0, ne, C.E, false, 0.f);
   const int N = n + p;
-  const bool ok = signed_cholesky<T, RPL>(C.M, N, n, C.iflag);
+  const bool ok = signed_cholesky<T, RPL>(C.M, N, n, C.iflag, dyn);
   make_dinv<T>(C, N);
   if (m) {
     const lf *hv[1] = {C.h};
@@ -1350,7 +1644,7 @@ __device__ __noinline__ int newton_standard(CT &Cin_, float mu, int kt_mode, flo
   __syncthreads();
   const int N = n + p;
   assemble<T>(C, 0, ne, C.E, false, delta_reg);
-  const bool ok = signed_cholesky<T, RPL>(C.M, N, n, C.iflag);
+  const bool ok = signed_cholesky<T, RPL>(C.M, N, n, C.iflag, false);
   const double dn = n, dm = m, dp = p, dN = N;
   work += 2.0 * dn * dn + 4.0 * dm * dn + 4.0 * dp * dn;
   work += dm * dn * (dn + 1.0) + dN * dN * dN / 3.0;
@@ -1482,7 +1776,7 @@ QPD void load_vectors(CT &C) {
   for (int i = tid; i < C.n; i += T) C.q[i] = C.q_g[i];
   for (int i = tid; i < C.m; i += T) C.h[i] = C.h_g[i];
   for (int i = tid; i < C.p; i += T) C.b[i] = C.b_g[i];
-  if (tid < kNB) C.zrow[tid] = 0.f;
+  if (tid < kNB) C.mz[tid] = 0.f;
   __syncthreads();
 }
 
@@ -1527,7 +1821,7 @@ __device__ __noinline__ bool adjoint(CT &Cin_, bool bounded, const gf *gx, const
     ok = factor_bounded<T, RPL>(C, nb, ne, C.t1, delta_reg, &reg);
   } else {
     assemble<T>(C, nb, ne, C.t1, false, 0.f);
-    ok = signed_cholesky<T, RPL>(C.M, N, n, C.iflag);
+    ok = signed_cholesky<T, RPL>(C.M, N, n, C.iflag, false);
   }
   const int nref = refine_steps + 2;
   const double dn = n, dN = N;
@@ -1668,6 +1962,10 @@ QPD void qp_body(const Params &P) {
   C.b_g = (const gf *)bp;
   C.G = (const gf *)Gp;
   C.h_g = (const gf *)hp;
+  if constexpr (MODE == kServe) C.amode = (P.desc[qi].flags >> 1) & 3;
+  else C.amode = P.asm_mode;
+  // split-product assembly is refined against the exact operator
+  const int refine = C.amode == 1 ? max(P.refine, 1) : P.refine;
   const int tid = threadIdx.x;
   const bool bounded = P.form == 0;
 #ifdef QPK_PHASE_TIMING
@@ -1689,7 +1987,7 @@ QPD void qp_body(const Params &P) {
     gf *st = (gf *)d.state;
     bool ok = true;
     if (d.flags & 1) {
-      ok = initialize<T, RPL>(C, work);
+      ok = initialize<T, RPL>(C, work, bounded);
     } else {
       for (int i = tid; i < n; i += T) C.x[i] = st[i];
       for (int k = tid; k < p; k += T) C.y[k] = st[n + k];
@@ -1703,7 +2001,7 @@ QPD void qp_body(const Params &P) {
       status = mkstatus(ST_FACT, SG_PRED);
     } else {
       status = newton_loop<T, RPL>(C, bounded, P.max_iter, P.tol, P.pc ? 0 : 1, P.sigma, 0.f,
-                                   P.delta_reg, P.refine, work, iters, res);
+                                   P.delta_reg, refine, work, iters, res);
     }
     for (int i = tid; i < n; i += T) st[i] = C.x[i];
     for (int k = tid; k < p; k += T) st[n + k] = C.y[k];
@@ -1717,14 +2015,14 @@ QPD void qp_body(const Params &P) {
       *d.res = res;
     }
   } else if constexpr (MODE == kSolve) {
-    const bool ok = initialize<T, RPL>(C, work);
+    const bool ok = initialize<T, RPL>(C, work, bounded);
     QPK_PT(C, PH_INIT);
     if (!ok) {
       status = mkstatus(ST_FACT, SG_PRED);
       res = __int_as_float(0x7fc00000);
     } else {
       status = newton_loop<T, RPL>(C, bounded, P.max_iter, P.tol, P.pc ? 0 : 1, P.sigma, 0.f,
-                                   P.delta_reg, P.refine, work, iters, res);
+                                   P.delta_reg, refine, work, iters, res);
     }
     gf *xo = (gf *)P.x + qi * (size_t)n;
     for (int i = tid; i < n; i += T) xo[i] = C.x[i];
@@ -1749,11 +2047,11 @@ QPD void qp_body(const Params &P) {
     }
     __syncthreads();
     status = newton_loop<T, RPL>(C, bounded, P.relax_max_iter, P.relax_tol, 2, 0.f, P.kappa_relax,
-                                 P.delta_reg, P.refine, work, iters, res);
+                                 P.delta_reg, refine, work, iters, res);
     const gf *gx = (const gf *)P.gx + qi * (size_t)n;
     const gf *gy = P.gy ? (const gf *)P.gy + qi * (size_t)p : nullptr;
     const gf *gz = P.gz ? (const gf *)P.gz + qi * (size_t)m : nullptr;
-    const bool ok = adjoint<T, RPL>(C, bounded, gx, gy, gz, P.delta_reg, P.refine, work);
+    const bool ok = adjoint<T, RPL>(C, bounded, gx, gy, gz, P.delta_reg, refine, work);
     QPK_PT(C, PH_BWD);
     if (!ok) status = mkstatus(ST_FACT, SG_BWD);
     __syncthreads();

@@ -10,16 +10,22 @@ size_t lds_bytes(int n, int m, int p, int kb, bool m_in_lds, int threads) {
 
 int64_t ws_floats(int n, int m, int p, int kb) {
   const Layout L = make_layout(n, m, p, kb, false, 128);
-  return (int64_t)al4(moff(L.Nmax) + 16);
+  return (int64_t)al4(moff(L.Nmax) + kNB);
 }
 
 size_t lds_limit() { return 160 * 1024; }
+
+bool mfma_stage_fits(int n, int m, int p, int kb, bool m_in_lds, int threads) {
+  const Layout L = make_layout(n, m, p, kb, m_in_lds, threads);
+  return stage_floats(n) <= L.stg_len;
+}
 
 #define QPK_EXTERN(TT, RR) \
   extern template hipError_t launch_t<TT, RR>(const Params &, bool, size_t, int, hipStream_t);
 QPK_EXTERN(128, 1) QPK_EXTERN(128, 2) QPK_EXTERN(128, 4) QPK_EXTERN(128, 8)
 QPK_EXTERN(256, 1) QPK_EXTERN(256, 2) QPK_EXTERN(256, 4) QPK_EXTERN(256, 8)
 QPK_EXTERN(512, 1) QPK_EXTERN(512, 2) QPK_EXTERN(512, 4) QPK_EXTERN(512, 8)
+QPK_EXTERN(512, 16)
 #undef QPK_EXTERN
 
 hipError_t launch(const Params &P, int threads, bool m_in_lds, size_t lds, int grid,
@@ -32,6 +38,8 @@ hipError_t launch(const Params &P, int threads, bool m_in_lds, size_t lds, int g
     if (rpl <= 2) return launch_t<TT, 2>(P, m_in_lds, lds, grid, stream); \
     if (rpl <= 4) return launch_t<TT, 4>(P, m_in_lds, lds, grid, stream); \
     if (rpl <= 8) return launch_t<TT, 8>(P, m_in_lds, lds, grid, stream); \
+    if (rpl <= 16 && TT == 512)                                           \
+      return launch_t<512, 16>(P, m_in_lds, lds, grid, stream);           \
     return hipErrorInvalidValue;                                          \
   }
   QPK_DISPATCH(128)

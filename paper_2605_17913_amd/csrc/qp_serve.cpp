@@ -200,7 +200,7 @@ void scheduler(qpx_server *S) {
       char *base = S->arena_dev + r->off;
       qpk::SlotDesc &d = S->h_desc[k];
       d.n = r->n; d.m = r->m; d.p = r->p; d.kb = r->plan.kb;
-      d.flags = r->fresh ? 1 : 0;
+      d.flags = (r->fresh ? 1 : 0) | (r->plan.amode << 1);
       d.Q = (const float *)(base + r->o_Q); d.q = (const float *)(base + r->o_q);
       d.A = r->p ? (const float *)(base + r->o_A) : nullptr;
       d.b = r->p ? (const float *)(base + r->o_b) : nullptr;

@@ -36,6 +36,28 @@ def test_default_opts():
     o = qpx.default_opts()
     assert o.form == 0 and o.max_iter == 100 and abs(o.tol - 1e-5) < 1e-12
     assert o.pc == 1 and abs(o.sigma - 0.1) < 1e-7 and abs(o.kappa_relax - 1e-4) < 1e-10
+    assert o.assembly == qpx.ASSEMBLY["auto"]
+
+
+def _struct_fields(name):
+    import re
+    text = open(HEADER).read()
+    body = re.search(r"typedef struct \{([^{}]*)\} " + name + ";", text).group(1)
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    names = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if decl:
+            names += [re.findall(r"\w+", piece)[-1] for piece in decl.split(",")]
+    return names
+
+
+def test_binding_structs_match_the_header():
+    # the ctypes mirrors must list the header's fields in the header's order
+    for cname, py in (("qp_batch", qpx._Batch), ("qp_opts", qpx._Opts), ("qp_out", qpx._Out),
+                      ("qp_grads", qpx._Grads), ("qp_server_opts", qpx._ServerOpts),
+                      ("qp_timing", qpx._Timing)):
+        assert _struct_fields(cname) == [f[0] for f in py._fields_], cname
 
 
 def test_null_arguments_are_rejected_on_the_host():

@@ -1,0 +1,77 @@
+"""GPU checks of the paper's ablation (section 6.1, appendix D) on polytope
+projection instances: the bounded (implicit) form solves and differentiates
+every instance in FP32, its gradients match the FP64 oracle's IFT gradient at
+the same kappa_relax, and as kappa_relax shrinks they approach the
+hard-projection reference J_hard v (eq. hard-jacobian).  The standard arm runs
+on the same inputs; its failure counts are reported, not asserted (the
+paper's rates are for its own generator and hardware)."""
+import numpy as np
+import pytest
+
+import qpgen
+from oracle import gradients
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _instances(n=20, n_ineq=25, n_act=10, count=12, seed=0):
+    insts = []
+    for k, d in enumerate(np.logspace(-2, 2, count)):
+        P = qpgen.projection(1, n, n_ineq, n_act, float(d), seed * 100 + k)
+        v = np.random.default_rng(seed * 31 + k).standard_normal(n).astype(np.float32)
+        insts.append((P, v))
+    return insts
+
+
+def _run(insts, form, kr, tol):
+    import paper_2605_17913_amd as qpx
+    dev = torch.device("cuda:0")
+    cat = lambda key: torch.from_numpy(np.concatenate([getattr(P, key) for P, _ in insts])).to(dev)
+    Q, q, G, h = cat("Q"), cat("q"), cat("G"), cat("h")
+    sol = qpx.solve(Q, q, None, None, G, h, form=form, tol=tol)
+    gv = torch.from_numpy(np.stack([v for _, v in insts])).to(dev)
+    g = qpx.backward(Q, q, None, None, G, h, sol, gv, form=form, kappa_relax=kr, relaxed=True)
+    torch.cuda.synchronize()
+    return (sol["status"].cpu().numpy(), g["relaxed"]["status"].cpu().numpy(),
+            -g["q"].cpu().numpy().astype(np.float64))
+
+
+def test_bounded_form_matches_oracle_on_projection():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    insts = _instances()
+    st, rst, grad = _run(insts, "bounded", 1e-4, 1e-5)
+    assert np.all((st & 0xff) == 0) and np.all((rst & 0xff) <= 1)
+    for k, (P, v) in enumerate(insts):
+        ref, _ = gradients.grad_at_relaxed(*P.one(0), 1e-4, v.astype(np.float64))
+        err = np.linalg.norm(grad[k] + ref["q"]) / max(1e-3, np.linalg.norm(ref["q"]))
+        assert err <= 1e-3, (k, err)
+
+
+def test_bounded_gradient_tracks_the_relaxation_floor():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    insts = _instances(count=8, seed=1)
+    hard = []
+    for P, v in insts:
+        Ga = P.G[0, :10].astype(np.float64)
+        Jh = np.eye(20) - Ga.T @ np.linalg.solve(Ga @ Ga.T, Ga)
+        hard.append(Jh @ v.astype(np.float64))
+    med = []
+    for kr in (1e-2, 1e-4, 1e-6):
+        st, rst, grad = _run(insts, "bounded", kr, min(kr, 1e-5))
+        assert np.all((st & 0xff) <= 1) and np.all((rst & 0xff) <= 1)
+        errs = [np.linalg.norm(grad[k] - hard[k]) / np.linalg.norm(hard[k]) for k in range(len(insts))]
+        med.append(float(np.median(errs)))
+    assert med[0] > med[1] > med[2], med
+    assert med[2] < 1e-2, med
+
+
+def test_standard_form_runs_on_the_same_inputs():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    insts = _instances()
+    st, rst, grad = _run(insts, "standard", 1e-4, 1e-5)
+    # every outcome is a valid status code with a stage attribution
+    assert np.all((st & 0xff) <= 3) and np.all(((st >> 8) & 0xff) <= 7)
