@@ -10,8 +10,14 @@ to kappa_relax = 1e-4 (Algorithm 2), adjoint solve and parameter gradients
 
 Printed: one JSON line.  value = fwd+bwd QPs per second of the timed steps;
 extra fields give forward-only solves/s, the roofline of the dominant kernel
-(the fused solve kernel), the FP64 oracle timed on the host cores and the
-standard-form ablation on the same inputs.
+(the fused solve kernel), the FP64 oracle timed on the host cores, the
+standard-form ablation on the same inputs, the serving loop's throughput and
+p50/p99 latency, and the rates of the differentiation (n=100) and
+ill-conditioned (n=256) configurations.
+
+--calibrate-copy runs only a device-to-device copy of a known size; its
+FETCH_SIZE / WRITE_SIZE counters give the scale that turns those counters
+into HBM bytes for the solve kernel's measured traffic.
 """
 from __future__ import annotations
 
@@ -21,43 +27,113 @@ import os
 import sys
 import time
 
+import hashlib
+
 import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+
+METRIC = "QP solves/s + fwd+bwd/s at 1e-5 KKT residual (FP32 vs plain); p50/p99 latency"
+KERNEL_SRC = os.path.join(ROOT, "paper_2605_17913_amd", "csrc", "qp_kernel_impl.hpp")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_qp_solve_kernel_n50_m100_p10.json")
 
 PEAK_ALU = 78.6      # TFLOP/s: 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz (FP32 FMA, unpacked)
 PEAK_ALU_PACKED = 157.3
 PEAK_HBM = 8000.0    # GB/s
 
 
-def _oracle_worker(problems):
+def _oracle_worker(work):
+    """One step of the workload per QP with the FP64 oracle: solve to 1e-5,
+    relax to kappa_relax = 1e-4 from that point, IFT vector-Jacobian product."""
     import threadpoolctl
-    from oracle import implicit
+    from oracle import gradients, implicit
     with threadpoolctl.threadpool_limits(1):
         t0 = time.perf_counter()
-        for prob in problems:
-            implicit.solve_qp(*prob, tol=1e-5)
-        return time.perf_counter() - t0, len(problems)
+        for prob, gx in work:
+            r = implicit.solve_qp(*prob, tol=1e-5)
+            gradients.grad_at_relaxed(*prob, 1e-4, gx, warm=(r.x, r.y, r.z, r.s))
+        return time.perf_counter() - t0, len(work)
 
 
-def cpu_baseline(P, budget_s=15.0):
-    """The FP64 oracle (Algorithm 1, dense LU on the uncondensed system) on a
+def cpu_baseline(P, gx, budget_s=15.0):
+    """The FP64 oracle (Algorithm 1 with dense LU on the uncondensed system,
+    Algorithm 2, the IFT product from the transposed standard Jacobian) on a
     bounded sample of the same workload, one QP per worker process."""
     import multiprocessing as mp
     cores = min(16, os.cpu_count() or 1)
-    t, _ = _oracle_worker([P.one(0)])  # calibrate
+    t, _ = _oracle_worker([(P.one(0), gx[0])])  # calibrate
     n_qp = int(min(P.B, max(cores, budget_s * cores / max(t, 1e-4))))
-    chunks = [[P.one(i) for i in range(c, n_qp, cores)] for c in range(cores)]
+    chunks = [[(P.one(i), gx[i]) for i in range(c, n_qp, cores)] for c in range(cores)]
     t0 = time.perf_counter()
     with mp.get_context("spawn").Pool(cores) as pool:
         res = pool.map(_oracle_worker, [c for c in chunks if c])
     wall = time.perf_counter() - t0
     done = sum(r[1] for r in res)
     busy = max(r[0] for r in res)
-    return {"value": round(done / busy, 2), "unit": "solves/s", "cores": cores, "kind": "oracle",
-            "sample": f"first {done} of the {P.B} QPs, FP64 oracle solve to tol 1e-5, "
-                      f"{cores} worker processes with 1 BLAS thread each ({wall:.1f} s wall)"}
+    return {"value": round(done / busy, 2), "unit": "QPs/s", "cores": cores, "kind": "oracle",
+            "sample": f"first {done} of the {P.B} QPs, FP64 oracle solve to tol 1e-5 + relax to "
+                      f"kappa 1e-4 + IFT gradient, {cores} worker processes with 1 BLAS thread "
+                      f"each ({wall:.1f} s wall)"}
+
+
+def kernel_source_hash():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(launch_s):
+    """HBM traffic of the solve kernel from the committed counter runs, or
+    None when the kernel source has changed since they were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    byts = t["bytes_per_launch"]
+    return {"bytes_per_launch": byts, "GB_per_s": round(byts / launch_s / 1e9, 1),
+            "hbm_frac": round(byts / launch_s / 1e9 / PEAK_HBM, 4), "source": os.path.basename(TRAFFIC_FILE)}
+
+
+def calibrate_copy(mib=512, reps=5):
+    """Device-to-device copies of a known size (for the counter scale)."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    return {"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "reps": reps}
+
+
+def config_rate(qpx, torch, P, steps=3, backward=True, **kw):
+    """Solves/s (and fwd+bwd/s) of one extra configuration, inputs resident."""
+    dev = torch.device("cuda:0")
+    Q, q, A, b, G, h = (torch.from_numpy(a).to(dev) for a in P.arrays())
+    import qpgen
+    gx = torch.from_numpy(qpgen.upstream(P.B, P.Q.shape[1], 11)).to(dev)
+    opts = qpx.make_opts(tol=1e-5, kappa_relax=1e-4, **kw)
+    sol = qpx.solve(Q, q, A, b, G, h, opts=opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sol = qpx.solve(Q, q, A, b, G, h, opts=opts)
+    torch.cuda.synchronize()
+    t_fwd = (time.perf_counter() - t0) / steps
+    out = {"solves_per_s": round(P.B / t_fwd, 1),
+           "converged_frac": float(np.mean((sol["status"].cpu().numpy() & 0xFF) == 0)),
+           "iters_mean": float(sol["iters"].float().mean().item())}
+    if backward:
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            s2 = qpx.solve(Q, q, A, b, G, h, opts=opts)
+            qpx.backward(Q, q, A, b, G, h, s2, gx, opts=opts)
+        torch.cuda.synchronize()
+        out["fwd_bwd_per_s"] = round(P.B / ((time.perf_counter() - t0) / steps), 1)
+    return out
 
 
 def serving_bench(n_requests=1200, seed=7, rates=(0.5, 0.9), max_slots=512, iters_per_step=4):
@@ -207,6 +283,10 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--ablation", action="store_true",
                     help="run the appendix D projection sweeps instead of the benchmark")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the differentiation and ill-conditioned configurations")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run device copies of a known size (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -220,12 +300,16 @@ def main():
     if args.ablation:
         print(json.dumps({"ablation": ablation()}), flush=True)
         return
+    if args.calibrate_copy:
+        print(json.dumps({"calibrate_copy": calibrate_copy()}), flush=True)
+        return
 
     B, n, m, p = args.batch, 50, 100, 10
     dev = torch.device("cuda:0")
     P = qpgen.random_feasible(B, n, m, p, args.seed)
     Q, q, A, b, G, h = (torch.from_numpy(a).to(dev) for a in P.arrays())
-    gx = torch.from_numpy(qpgen.upstream(B, n, args.seed + 1)).to(dev)
+    gx_h = qpgen.upstream(B, n, args.seed + 1)
+    gx = torch.from_numpy(gx_h).to(dev)
     opts = qpx.make_opts(tol=1e-5, kappa_relax=1e-4)
 
     def step(timing=None):
@@ -264,23 +348,25 @@ def main():
     achieved = work_fwd / fwd_avg / 1e12
 
     out = {
-        "metric": "QP fwd+bwd/s at 1e-5 scaled KKT residual (FP32, implicit complementarity)",
+        "metric": METRIC,
         "value": round(value, 1),
         "unit": "QPs/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"random feasible QPs B={B} n={n} m={m} p={p}, solve to 1e-5 + "
-                               "relax to kappa 1e-4 + IFT backward", "batch": B, "n": n, "m": m,
-                   "p": p},
+        "config": {"workload": f"random feasible QPs B={B} n={n} m={m} p={p}, solve to 1e-5 "
+                               "(scaled KKT residual) + relax to kappa 1e-4 + IFT backward; "
+                               "value = fwd+bwd QPs/s", "batch": B, "n": n, "m": m, "p": p},
         "solves_per_s": round(B / fwd_avg, 1),
         "fwd_ms": round(fwd_avg * 1e3, 3), "bwd_ms": round(bwd_avg * 1e3, 3),
         "converged_frac": float(np.mean((status & 0xff) == 0)),
         "iters_mean": float(np.mean(iters)), "iters_max": int(np.max(iters)),
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_ALU,
-                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_ALU, 4), "traffic": None,
-                     "kernel": "qp_kernel (fused solve)", "peak_packed_fp32": PEAK_ALU_PACKED},
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_ALU, 4),
+                     "traffic": measured_traffic(fwd_avg),
+                     "kernel": "qp_solve_kernel<256, 2, true> (fused solve, one launch per step)",
+                     "launch_ms": round(fwd_avg * 1e3, 3), "peak_packed_fp32": PEAK_ALU_PACKED},
     }
     if not args.no_ablation:
         std = qpx.solve(Q, q, A, b, G, h, form="standard", tol=1e-5)
@@ -288,10 +374,17 @@ def main():
         s2 = std["status"].cpu().numpy()
         out["standard_form"] = {"converged_frac": float(np.mean((s2 & 0xff) == 0)),
                                 "nonfinite_or_factor_fail_frac": float(np.mean((s2 & 0xff) >= 2))}
+    if not args.no_extra:
+        out["other_configs"] = {
+            "differentiation n=100 m=200 p=20 B=1024": config_rate(
+                qpx, torch, qpgen.random_feasible(1024, 100, 200, 20, 3)),
+            "ill-conditioned degenerate n=256 m=512 p=32 B=512": config_rate(
+                qpx, torch, qpgen.ill_conditioned(512, 256, 512, 32, 4), steps=1, backward=False),
+        }
     if not args.no_serving:
         out["serving"] = serving_bench()
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(P)
+        out["cpu_baseline"] = cpu_baseline(P, gx_h)
     print(json.dumps(out), flush=True)
 
 

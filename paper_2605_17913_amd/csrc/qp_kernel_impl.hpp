@@ -188,7 +188,8 @@ struct Layout {
   int tGz, tAy;
   int t0, t1, u0, u1, dv0, dv1, dinv;
   int part, red;
-  int w0, w1, rr, dd;  // rhs copies / residual for refinement; FP64 scratch
+  int w0, w1, rr, rd, dd;  // rhs copies / residual and last correction of
+                           // the refinement; FP64 scratch
   int pan;             // (unused)
   int role, bidx, elist, iflag;
   int stg, stg_len;  // assembly staging: the span u0 .. end of dd, which
@@ -217,7 +218,7 @@ __host__ __device__ inline Layout make_layout(int n, int m, int p, int kb, bool 
   L.dv0 = take(m); L.dv1 = take(m); L.dinv = take(L.Nmax);
   // partial sums (2 floats or 1 double per thread) and reduction scratch
   L.part = take(2 * T); L.red = take((T / 64) * 16);
-  L.w0 = L.t0; L.w1 = L.t1; L.rr = take(L.Nmax);
+  L.w0 = L.t0; L.w1 = L.t1; L.rr = take(L.Nmax); L.rd = take(L.Nmax);
   L.dd = take(2 * (2 * m + p + n + 8));
   L.pan = take(4);
   L.role = take(m); L.bidx = take(m); L.elist = take(m); L.iflag = take(16);
@@ -496,7 +497,8 @@ QPD bool factor_panel(MF *M, int N, int npos, int k0, bool dyn, float &pmax, int
 // zeros.  Returns false (uniformly) if a pivot sg_j * a_jj is not a positive
 // finite number.  With dyn, numerically zero pivots are regularised (see
 // factor_panel) and flag[2] receives their count.  flag[0] is the failure
-// flag; flag[1] is left alone.  RPL = rows per lane, >= ceil(N / 64).
+// flag, flag[4] the largest accepted pivot (float bits); flag[1] and flag[3]
+// are left alone.  RPL = rows per lane, >= ceil(N / 64).
 template <int T, int RPL, class MF>
 __device__ __noinline__ bool signed_cholesky(MF *M, int N, int npos, li *flag, bool dyn) {
   M = rflp(M); N = rfl(N); npos = rfl(npos); flag = rflp(flag); dyn = rfl(dyn);
@@ -552,7 +554,10 @@ __device__ __noinline__ bool signed_cholesky(MF *M, int N, int npos, li *flag, b
     }
     __syncthreads();
   }
-  if (tid == 0) flag[2] = nreg;
+  if (tid == 0) {
+    flag[2] = nreg;
+    flag[4] = __float_as_int(pmax);  // largest accepted pivot (retry scale)
+  }
   __syncthreads();
   return flag[0] == 0;
 }
@@ -725,7 +730,7 @@ struct Ctx {
   lf *tGz, *tAy;
   lf *t0, *t1, *u0, *u1, *dv0, *dv1, *dinv;
   lf *part, *red;
-  lf *w0, *w1, *rr, *pan;
+  lf *w0, *w1, *rr, *rd, *pan;
   MF *mz;    // 16 zeros after M's last row (same address space as M)
   ldd *dd;
   li *role, *bidx, *elist, *iflag;
@@ -748,7 +753,7 @@ QPD void init_ctx(Ctx<MF> &C, lf *sm, const Layout &L, MF *Mptr) {
   C.t0 = sm + L.t0; C.t1 = sm + L.t1; C.u0 = sm + L.u0; C.u1 = sm + L.u1;
   C.dv0 = sm + L.dv0; C.dv1 = sm + L.dv1; C.dinv = sm + L.dinv;
   C.part = sm + L.part; C.red = sm + L.red;
-  C.w0 = sm + L.w0; C.w1 = sm + L.w1; C.rr = sm + L.rr; C.pan = sm + L.pan;
+  C.w0 = sm + L.w0; C.w1 = sm + L.w1; C.rr = sm + L.rr; C.rd = sm + L.rd; C.pan = sm + L.pan;
   C.mz = Mptr + moff(L.Nmax);
   C.dd = reinterpret_cast<ldd *>(sm + L.dd);
   C.role = reinterpret_cast<li *>(sm + L.role);
@@ -778,7 +783,8 @@ QPD Ctx<MF> uctx(const Ctx<MF> &I) {
   C.t0 = rflp(I.t0); C.t1 = rflp(I.t1); C.u0 = rflp(I.u0); C.u1 = rflp(I.u1);
   C.dv0 = rflp(I.dv0); C.dv1 = rflp(I.dv1); C.dinv = rflp(I.dinv);
   C.part = rflp(I.part); C.red = rflp(I.red);
-  C.w0 = rflp(I.w0); C.w1 = rflp(I.w1); C.rr = rflp(I.rr); C.pan = rflp(I.pan); C.mz = rflp(I.mz);
+  C.w0 = rflp(I.w0); C.w1 = rflp(I.w1); C.rr = rflp(I.rr); C.rd = rflp(I.rd); C.pan = rflp(I.pan);
+  C.mz = rflp(I.mz);
   C.dd = rflp(I.dd);
   C.role = rflp(I.role); C.bidx = rflp(I.bidx); C.elist = rflp(I.elist); C.iflag = rflp(I.iflag);
   C.stg = rflp(I.stg); C.amode = rfl(I.amode);
@@ -1263,15 +1269,21 @@ __device__ __noinline__ void solve2(CT &Cin_, int N, bool both) {
 // Dl = D/E on bounded border rows and 0 on equality rows, against the
 // operator WITHOUT any regularisation, with the residual w - K u
 // accumulated in FP64 from the original Q, G, A.  Each step solves for the
-// correction with the existing factor (one wave) and adds it.
+// correction with the existing factor (one wave) and adds it.  A step whose
+// residual is not smaller than the previous one is taken back and ends the
+// refinement.  Returns the largest ratio of successive residual max-norms
+// (0 after a single step): above 1/2 the factor is too coarse a
+// preconditioner for this system.
+constexpr float kRefineSlow = 0.5f;
 template <int T, int RPL, class CT>
-__device__ __noinline__ void refine(CT &Cin_, int nb, bool bounded, const lf *w, lf *u, int steps) {
+__device__ __noinline__ float refine(CT &Cin_, int nb, bool bounded, const lf *w, lf *u, int steps) {
   CT C = uctx(Cin_);
   nb = rfl(nb); bounded = rfl(bounded); w = rflp(w); u = rflp(u); steps = rfl(steps);
   const int n = C.n, m = C.m, p = C.p, tid = threadIdx.x, N = n + nb + p;
   ldd *gx = C.dd, *ax = C.dd + m, *phi = C.dd + m + p, *kx = C.dd + 2 * m + p;
   ldd *pd = reinterpret_cast<ldd *>(C.part);
   lf *r = C.rr;
+  float prev = 0.f, worst = 0.f;
   for (int it = 0; it < steps; ++it) {
     if (m) rowdot_d<T>(C.G, n, m, n, u, gx);
     if (p) rowdot_d<T>(C.A, n, p, n, u, ax);
@@ -1293,21 +1305,44 @@ __device__ __noinline__ void refine(CT &Cin_, int nb, bool bounded, const lf *w,
     }
     for (int a = tid; a < p; a += T) r[n + nb + a] = (float)((double)w[n + nb + a] - ax[a]);
     __syncthreads();
+    // residual max-norm (a non-finite residual counts as no progress)
+    float mx[2] = {0.f, 0.f};
+    for (int j = tid; j < N; j += T) {
+      const float a = fabsf(r[j]);
+      mx[0] = fmaxf(mx[0], a);
+      if (!(a <= FLT_MAX)) mx[1] = 1.f;
+    }
+    block_reduce<T, OpMax, 2>(mx, C.red);
+    const float nrm = mx[1] != 0.f ? kBig : mx[0];
+    if (it > 0) {
+      worst = fmaxf(worst, prev > 0.f ? nrm / prev : 0.f);
+      if (!(nrm < prev)) {
+        // the last correction did not help: take it back and stop
+        for (int j = tid; j < N; j += T) u[j] -= C.rd[j];
+        __syncthreads();
+        break;
+      }
+    }
+    prev = nrm;
     if (threadIdx.x < 64) signed_solve_wave<RPL>(C.M, N, n, C.dinv, r, C.mz);
     __syncthreads();
-    for (int j = tid; j < N; j += T) u[j] += r[j];
+    for (int j = tid; j < N; j += T) {
+      C.rd[j] = r[j];
+      u[j] += r[j];
+    }
     __syncthreads();
   }
+  return worst;
 }
 
 
 // Add -delta to the diagonal of the border block, with delta = rel * (largest
-// squared border-row norm) / (largest diagonal of H): a Tikhonov floor on the
-// Schur complement Dl + C H^-1 C' scaled like its entries.
+// squared border-row norm) / (largest diagonal of H), and at least floor_abs:
+// a Tikhonov floor on the Schur complement Dl + C H^-1 C'.
 template <int T, class CT>
-__device__ __noinline__ void border_delta(CT &Cin_, int nb, float rel) {
+__device__ __noinline__ void border_delta(CT &Cin_, int nb, float rel, float floor_abs) {
   CT C = uctx(Cin_);
-  nb = rfl(nb); rel = rflf(rel);
+  nb = rfl(nb); rel = rflf(rel); floor_abs = rflf(floor_abs);
   const int n = C.n, K = nb + C.p, tid = threadIdx.x;
   float mx[2] = {0.f, 0.f};
   for (int j = tid; j < n; j += T) mx[0] = fmaxf(mx[0], C.M[moff(j) + j]);
@@ -1320,27 +1355,30 @@ __device__ __noinline__ void border_delta(CT &Cin_, int nb, float rel) {
     mx[1] = fmaxf(mx[1], ss);
   }
   block_reduce<T, OpMax, 2>(mx, C.red);
-  const float delta = fmaxf(rel * mx[1] / fmaxf(mx[0], 1e-30f), 1e-30f);
+  const float delta = fmaxf(fmaxf(rel * mx[1] / fmaxf(mx[0], 1e-30f), floor_abs), 1e-30f);
   for (int k = tid; k < K; k += T) C.M[moff(n + k) + n + k] -= delta;
   __syncthreads();
 }
 
 // Assemble and factor the bounded-form matrix.  On a pivot breakdown the
-// matrix is rebuilt with a border floor (relative 1e-6 at least) and
-// factored again; *regularised tells the caller to refine against the
-// unregularised operator.
+// matrix is rebuilt with a border floor and factored again; *regularised
+// tells the caller to refine against the unregularised operator.
+constexpr float kRetryReg = 1e-4f;
 template <int T, int RPL, class CT>
 QPD bool factor_bounded(CT &C, int nb, int ne, const lf *wts, float delta_rel, bool *regularised) {
   const int N = C.n + nb + C.p;
   assemble<T>(C, nb, ne, wts, true, 0.f);
-  if (delta_rel > 0.f) border_delta<T>(C, nb, delta_rel);
+  if (delta_rel > 0.f) border_delta<T>(C, nb, delta_rel, 0.f);
   QPK_PT(C, PH_ASM);
   bool ok = signed_cholesky<T, RPL>(C.M, N, C.n, C.iflag, true);
   QPK_PT(C, PH_FACT);
   *regularised = delta_rel > 0.f || C.iflag[2] > 0;
   if (!ok) {
+    // the floor is at least kRetryReg times the largest pivot the failed
+    // attempt accepted, i.e. scaled like the Schur complement's entries
+    const float pmax = __int_as_float(C.iflag[4]);
     assemble<T>(C, nb, ne, wts, true, 0.f);
-    border_delta<T>(C, nb, fmaxf(delta_rel, 1e-6f));
+    border_delta<T>(C, nb, fmaxf(delta_rel, 1e-6f), kRetryReg * pmax);
     ok = signed_cholesky<T, RPL>(C.M, N, C.n, C.iflag, true);
     *regularised = true;
   }
@@ -1527,35 +1565,51 @@ __device__ __noinline__ int newton_bounded(CT &Cin_, float &kappa, int kt_mode, 
   kappa = rflf(kappa); kt_mode = rfl(kt_mode); sigma = rflf(sigma); kr = rflf(kr);
   delta_reg = rflf(delta_reg); refine_steps = rfl(refine_steps);
   const int n = C.n, m = C.m, p = C.p, tid = threadIdx.x;
+  C.amode = rfl(C.iflag[3]);  // this QP's assembly arithmetic (may have fallen back)
   const int nb = partition_bounded<T>(C, kappa);
   const int ne = C.iflag[1];
   QPK_PT(C, PH_PART);
-  // weights E/D for eliminated rows (stored in t1 temporarily)
-  for (int i = tid; i < m; i += T) C.t1[i] = C.E[i] / C.D[i];
-  __syncthreads();
   const int N = n + nb + p;
-  bool reg = false;
-  const bool ok = factor_bounded<T, RPL>(C, nb, ne, C.t1, delta_reg, &reg);
   const double dn = n, dm = m, dp = p, dN = N;
   work += 2.0 * dn * dn + 4.0 * dm * dn + 4.0 * dp * dn;            // residuals
-  work += (double)ne * dn * (dn + 1.0) + dN * dN * dN / 3.0;        // assembly + factor
-  work += 2.0 * (2.0 * dN * dN + 4.0 * dm * dn);                    // two solves
-  if (!ok) { *stage = SG_PRED; return ST_FACT; }
-  make_dinv<T>(C, N);
-  rhs_bounded<T>(C, nb, kappa, nullptr, nullptr, nullptr, false);
-  QPK_PT(C, PH_RHS);
-  const int nref = reg ? max(refine_steps, 2) : refine_steps;
-  if (nref) {
-    for (int j = tid; j < N; j += T) { C.w0[j] = C.u0[j]; C.w1[j] = C.u1[j]; }
+  // Factor, solve and refine.  With split-product (BF16x3) assembly, a
+  // refinement that contracts by less than kRefineSlow per step means the
+  // assembly error is too large for this system's conditioning: the QP
+  // switches to FP32 matrix-core assembly and the step is redone.
+  bool ok = false;
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    // weights E/D for eliminated rows (in t1 until the right-hand sides)
+    for (int i = tid; i < m; i += T) C.t1[i] = C.E[i] / C.D[i];
     __syncthreads();
+    bool reg = false;
+    ok = factor_bounded<T, RPL>(C, nb, ne, C.t1, delta_reg, &reg);
+    work += (double)ne * dn * (dn + 1.0) + dN * dN * dN / 3.0;      // assembly + factor
+    work += 2.0 * (2.0 * dN * dN + 4.0 * dm * dn);                  // two solves
+    if (!ok) break;
+    make_dinv<T>(C, N);
+    rhs_bounded<T>(C, nb, kappa, nullptr, nullptr, nullptr, false);
+    QPK_PT(C, PH_RHS);
+    const int nref = (reg || C.amode == 1) ? max(refine_steps, 2) : refine_steps;
+    if (nref) {
+      for (int j = tid; j < N; j += T) { C.w0[j] = C.u0[j]; C.w1[j] = C.u1[j]; }
+      __syncthreads();
+    }
+    solve2<T, RPL>(C, N, true);
+    QPK_PT(C, PH_SOLVE);
+    if (nref) {
+      const float q0 = refine<T, RPL>(C, nb, true, C.w0, C.u0, nref);
+      const float q1 = refine<T, RPL>(C, nb, true, C.w1, C.u1, nref);
+      work += 2.0 * nref * (2.0 * dN * dN + 4.0 * dm * dn + 2.0 * dn * dn + 4.0 * dp * dn);
+      if (C.amode == 1 && !(fmaxf(q0, q1) <= kRefineSlow)) {
+        C.amode = 2;
+        if (tid == 0) C.iflag[3] = 2;
+        __syncthreads();
+        continue;
+      }
+    }
+    break;
   }
-  solve2<T, RPL>(C, N, true);
-  QPK_PT(C, PH_SOLVE);
-  if (nref) {
-    refine<T, RPL>(C, nb, true, C.w0, C.u0, nref);
-    refine<T, RPL>(C, nb, true, C.w1, C.u1, nref);
-    work += 2.0 * nref * (2.0 * dN * dN + 4.0 * dm * dn + 2.0 * dn * dn + 4.0 * dp * dn);
-  }
+  if (!ok) { *stage = SG_PRED; return ST_FACT; }
   QPK_PT(C, PH_REFINE);
   recover_bounded<T>(C, nb, true);
   QPK_PT(C, PH_RECOVER);
@@ -1816,29 +1870,48 @@ __device__ __noinline__ bool adjoint(CT &Cin_, bool bounded, const gf *gx, const
     for (int i = tid; i < m; i += T) C.E[i] = C.t1[i];
   __syncthreads();
   const int N = n + nb + p;
-  bool ok, reg = false;
-  if (bounded) {
-    ok = factor_bounded<T, RPL>(C, nb, ne, C.t1, delta_reg, &reg);
-  } else {
-    assemble<T>(C, nb, ne, C.t1, false, 0.f);
-    ok = signed_cholesky<T, RPL>(C.M, N, n, C.iflag, false);
-  }
   const int nref = refine_steps + 2;
   const double dn = n, dN = N;
-  work += (double)ne * dn * (dn + 1.0) + dN * dN * dN / 3.0 + 2.0 * dN * dN + 8.0 * m * dn;
-  work += nref * (2.0 * dN * dN + 2.0 * dn * dn + 8.0 * m * dn + 4.0 * p * dn);
-  if (!ok) return false;
-  make_dinv<T>(C, N);
+  const double wfac = (double)ne * dn * (dn + 1.0) + dN * dN * dN / 3.0 + 2.0 * dN * dN + 8.0 * m * dn;
+  const double wref = nref * (2.0 * dN * dN + 2.0 * dn * dn + 8.0 * m * dn + 4.0 * p * dn);
+  bool ok = false;
   if (bounded) {
-    rhs_bounded<T>(C, nb, kappa, gx, gz, gy, true);
-    for (int j = tid; j < N; j += T) C.w0[j] = C.u0[j];
-    __syncthreads();
-    solve2<T, RPL>(C, N, false);
-    refine<T, RPL>(C, nb, true, C.w0, C.u0, nref);
+    C.amode = rfl(C.iflag[3]);
+    // as in newton_bounded: fall back from split-product assembly when the
+    // refinement does not contract
+    for (int attempt = 0; attempt < 2; ++attempt) {
+      if (attempt) {
+        for (int i = tid; i < m; i += T) C.t1[i] = C.E[i] / C.D[i];
+        __syncthreads();
+      }
+      bool reg = false;
+      ok = factor_bounded<T, RPL>(C, nb, ne, C.t1, delta_reg, &reg);
+      work += wfac + wref;
+      if (!ok) break;
+      make_dinv<T>(C, N);
+      rhs_bounded<T>(C, nb, kappa, gx, gz, gy, true);
+      for (int j = tid; j < N; j += T) C.w0[j] = C.u0[j];
+      __syncthreads();
+      solve2<T, RPL>(C, N, false);
+      const float q = refine<T, RPL>(C, nb, true, C.w0, C.u0, nref);
+      if (C.amode == 1 && !(q <= kRefineSlow)) {
+        C.amode = 2;
+        if (tid == 0) C.iflag[3] = 2;
+        __syncthreads();
+        continue;
+      }
+      break;
+    }
+    if (!ok) return false;
     recover_bounded<T>(C, nb, false);
     // dz = E (dv + gz)
     for (int i = tid; i < m; i += T) C.dv0[i] = C.E[i] * (C.dv0[i] + (gz ? gz[i] : 0.f));
   } else {
+    assemble<T>(C, nb, ne, C.t1, false, 0.f);
+    ok = signed_cholesky<T, RPL>(C.M, N, n, C.iflag, false);
+    work += wfac + wref;
+    if (!ok) return false;
+    make_dinv<T>(C, N);
     // standard: [H A'; A 0][a; c] = [-gx - G' W gz; -gy], dz = W (G a + gz)
     for (int i = tid; i < m; i += T) C.t0[i] = gz ? C.E[i] * gz[i] : 0.f;
     __syncthreads();
@@ -1964,9 +2037,10 @@ QPD void qp_body(const Params &P) {
   C.h_g = (const gf *)hp;
   if constexpr (MODE == kServe) C.amode = (P.desc[qi].flags >> 1) & 3;
   else C.amode = P.asm_mode;
-  // split-product assembly is refined against the exact operator
-  const int refine = C.amode == 1 ? max(P.refine, 1) : P.refine;
+  const int refine = P.refine;
   const int tid = threadIdx.x;
+  // per-QP assembly mode for the Newton steps (a BF16x3 QP may fall back)
+  if (tid == 0) C.iflag[3] = C.amode;
   const bool bounded = P.form == 0;
 #ifdef QPK_PHASE_TIMING
   __shared__ long long pt_acc[PH_N];
