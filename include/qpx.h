@@ -100,14 +100,17 @@ typedef struct {
 
 /* Assembly of the (1,1) block of the reduced KKT matrix.  The factorisation,
  * solves and residuals are FP32 (FP64-accumulated residuals) in every mode.
- *  QPX_ASM_AUTO    QPX_ASM_BF16X3 for the bounded form when n >= 128 and the
- *                  staging buffer fits the workgroup's LDS, else QPX_ASM_FP32.
+ *  QPX_ASM_AUTO    QPX_ASM_MFMA_FP32 for the bounded form when n >= 128 and
+ *                  the staging buffer fits the workgroup's LDS, else
+ *                  QPX_ASM_FP32 (the fastest of the three at those sizes).
  *  QPX_ASM_FP32    FP32 fused multiply-adds on the vector ALUs.
  *  QPX_ASM_BF16X3  matrix cores: each operand split into two bfloat16 terms,
  *                  three products per pair accumulated in FP32 (relative
  *                  error about 2^-16 per product); every Newton and adjoint
- *                  solve then takes at least one step of iterative refinement
- *                  against the exact operator, which restores FP32 accuracy.
+ *                  solve then takes at least two steps of iterative
+ *                  refinement against the exact operator, which restores
+ *                  FP32 accuracy; a QP whose refinement contracts by less
+ *                  than 1/2 per step switches to QPX_ASM_MFMA_FP32.
  *  QPX_ASM_MFMA_FP32  matrix cores with FP32 inputs.
  * An explicit matrix-core mode for sizes whose staging does not fit returns
  * QPX_ERR_UNSUPPORTED. */

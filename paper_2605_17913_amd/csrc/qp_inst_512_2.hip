@@ -1,5 +1,7 @@
 // Instantiation of the fused kernel for 512 threads per QP and up to 128 rows of
 // the bordered KKT system.
+// small systems: phases inlined into the kernels
+#define QPK_INLINE_PHASES
 #include "qp_kernel_impl.hpp"
 
 namespace qpk {

@@ -52,6 +52,17 @@ namespace qpk {
 namespace {
 
 #define QPD __device__ __forceinline__
+// Attribute of the solver's phases (residuals, partition, assembly,
+// factorisation, solves, refinement, ...).  Small systems inline them into
+// the kernel: the calls' saved registers and context copies would otherwise
+// go through scratch memory.  Large systems keep them as separate functions,
+// which bounds register pressure and compile time; the instantiation unit
+// chooses by defining QPK_INLINE_PHASES.
+#ifdef QPK_INLINE_PHASES
+#define QPK_PHASE __device__ __forceinline__
+#else
+#define QPK_PHASE __device__ __noinline__
+#endif
 
 constexpr int kNB = 16;          // panel width of the blocked factorisation
 constexpr float kBig = 3.0e38f;
@@ -500,7 +511,7 @@ QPD bool factor_panel(MF *M, int N, int npos, int k0, bool dyn, float &pmax, int
 // flag, flag[4] the largest accepted pivot (float bits); flag[1] and flag[3]
 // are left alone.  RPL = rows per lane, >= ceil(N / 64).
 template <int T, int RPL, class MF>
-__device__ __noinline__ bool signed_cholesky(MF *M, int N, int npos, li *flag, bool dyn) {
+QPK_PHASE bool signed_cholesky(MF *M, int N, int npos, li *flag, bool dyn) {
   M = rflp(M); N = rfl(N); npos = rfl(npos); flag = rflp(flag); dyn = rfl(dyn);
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   // wave 0's running pivot scale and count of regularised pivots
@@ -796,7 +807,7 @@ QPD Ctx<MF> uctx(const Ctx<MF> &I) {
 // Returns the scaled residual measure (uniform); `bad` = a non-finite value
 // was seen.  complementarity: max(z s) (solve) or max|z s - kr| / kr (relax).
 template <int T, class CT>
-__device__ __noinline__ float residuals(CT &Cin_, bool bounded, float kappa, float kr, bool *bad) {
+QPK_PHASE float residuals(CT &Cin_, bool bounded, float kappa, float kr, bool *bad) {
   CT C = uctx(Cin_);
   bounded = rfl(bounded); kappa = rflf(kappa); kr = rflf(kr);
   const int n = C.n, m = C.m, p = C.p, tid = threadIdx.x;
@@ -897,7 +908,7 @@ QPD int compact_rows(const li *flag, int m, li *out, lf *red) {
 // number of bordered rows nb; fills E, D, c, role (border index or -1),
 // bidx (border rows), elist (eliminated rows) and iflag[1] = #eliminated.
 template <int T, class CT>
-__device__ __noinline__ int partition_bounded(CT &Cin_, float kappa) {
+QPK_PHASE int partition_bounded(CT &Cin_, float kappa) {
   CT C = uctx(Cin_);
   kappa = rflf(kappa);
   const int m = C.m, kb = C.kb, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -1117,7 +1128,7 @@ QPD void assemble_h_mfma(CT &C, int ne, const lf *wts) {
 // z/s standard); border rows = G[bidx] then A; Dl = dl (per border row) and
 // delta on the diagonal of the border block.
 template <int T, class CT>
-__device__ __noinline__ void assemble(CT &Cin_, int nb, int ne, const lf *wts, bool bounded, float delta) {
+QPK_PHASE void assemble(CT &Cin_, int nb, int ne, const lf *wts, bool bounded, float delta) {
   CT C = uctx(Cin_);
   nb = rfl(nb); ne = rfl(ne); wts = rflp(wts); bounded = rfl(bounded); delta = rflf(delta);
   const int n = C.n, p = C.p, tid = threadIdx.x;
@@ -1247,7 +1258,7 @@ QPD void make_dinv(CT &C, int N) {
 // Solve for both right-hand sides u0 and u1 (wave 0 and wave 1 in parallel
 // when the workgroup has two waves).
 template <int T, int RPL, class CT>
-__device__ __noinline__ void solve2(CT &Cin_, int N, bool both) {
+QPK_PHASE void solve2(CT &Cin_, int N, bool both) {
   CT C = uctx(Cin_);
   N = rfl(N); both = rfl(both);
   const int wid = threadIdx.x >> 6;
@@ -1276,7 +1287,7 @@ __device__ __noinline__ void solve2(CT &Cin_, int N, bool both) {
 // preconditioner for this system.
 constexpr float kRefineSlow = 0.5f;
 template <int T, int RPL, class CT>
-__device__ __noinline__ float refine(CT &Cin_, int nb, bool bounded, const lf *w, lf *u, int steps) {
+QPK_PHASE float refine(CT &Cin_, int nb, bool bounded, const lf *w, lf *u, int steps) {
   CT C = uctx(Cin_);
   nb = rfl(nb); bounded = rfl(bounded); w = rflp(w); u = rflp(u); steps = rfl(steps);
   const int n = C.n, m = C.m, p = C.p, tid = threadIdx.x, N = n + nb + p;
@@ -1340,7 +1351,7 @@ __device__ __noinline__ float refine(CT &Cin_, int nb, bool bounded, const lf *w
 // squared border-row norm) / (largest diagonal of H), and at least floor_abs:
 // a Tikhonov floor on the Schur complement Dl + C H^-1 C'.
 template <int T, class CT>
-__device__ __noinline__ void border_delta(CT &Cin_, int nb, float rel, float floor_abs) {
+QPK_PHASE void border_delta(CT &Cin_, int nb, float rel, float floor_abs) {
   CT C = uctx(Cin_);
   nb = rfl(nb); rel = rflf(rel); floor_abs = rflf(floor_abs);
   const int n = C.n, K = nb + C.p, tid = threadIdx.x;
@@ -1393,7 +1404,7 @@ QPD bool factor_bounded(CT &C, int nb, int ne, const lf *wts, float delta_rel, b
 //   u = [ -rho1 - G' psi ;  -rho2_B ;  -rho3 ].
 // rho2 of each column is left in dv0 / dv1 for the recovery.
 template <int T, class CT>
-__device__ __noinline__ void rhs_bounded(CT &Cin_, int nb, float kappa, const gf *gx, const gf *gz,
+QPK_PHASE void rhs_bounded(CT &Cin_, int nb, float kappa, const gf *gx, const gf *gz,
                      const gf *gy, bool adj) {
   CT C = uctx(Cin_);
   nb = rfl(nb); kappa = rflf(kappa); adj = rfl(adj);
@@ -1458,7 +1469,7 @@ __device__ __noinline__ void rhs_bounded(CT &Cin_, int nb, float kappa, const gf
 // Recover dv for the solved columns: eliminated rows dv = (G dx + rho2)/D,
 // border rows dv = du / E.  rho2 is read from dv0 / dv1 and overwritten.
 template <int T, class CT>
-__device__ __noinline__ void recover_bounded(CT &Cin_, int nb, bool both) {
+QPK_PHASE void recover_bounded(CT &Cin_, int nb, bool both) {
   CT C = uctx(Cin_);
   nb = rfl(nb); both = rfl(both);
   const int n = C.n, m = C.m, tid = threadIdx.x;
@@ -1502,7 +1513,7 @@ QPD int mkstatus(int st, int stage) { return st | (stage << 8); }
 // Initialisation (CVXOPT convention): solve [[Q+G'G, A'], [A, 0]] [x; y] =
 // [-q + G'h; b], zt = Gx - h, s = -zt, z = zt, each shifted positive.
 template <int T, int RPL, class CT>
-__device__ __noinline__ bool initialize(CT &Cin_, double &work, bool dyn) {
+QPK_PHASE bool initialize(CT &Cin_, double &work, bool dyn) {
   CT C = uctx(Cin_);
   dyn = rfl(dyn);
   const int n = C.n, m = C.m, p = C.p, tid = threadIdx.x;
@@ -1559,7 +1570,7 @@ __device__ __noinline__ bool initialize(CT &Cin_, double &work, bool dyn) {
 // Returns a status code (ST_CONV meaning "keep going"), with the stage in
 // *stage on failure.  Updates x, y, v, kappa, z, s.
 template <int T, int RPL, class CT>
-__device__ __noinline__ int newton_bounded(CT &Cin_, float &kappa, int kt_mode, float sigma, float kr,
+QPK_PHASE int newton_bounded(CT &Cin_, float &kappa, int kt_mode, float sigma, float kr,
                        float delta_reg, int refine_steps, double &work, int *stage) {
   CT C = uctx(Cin_);
   kappa = rflf(kappa); kt_mode = rfl(kt_mode); sigma = rflf(sigma); kr = rflf(kr);
@@ -1678,7 +1689,7 @@ __device__ __noinline__ int newton_bounded(CT &Cin_, float &kappa, int kt_mode, 
 
 // One Mehrotra predictor-corrector iteration of the standard form.
 template <int T, int RPL, class CT>
-__device__ __noinline__ int newton_standard(CT &Cin_, float mu, int kt_mode, float kr, float delta_reg, double &work,
+QPK_PHASE int newton_standard(CT &Cin_, float mu, int kt_mode, float kr, float delta_reg, double &work,
                         int *stage) {
   CT C = uctx(Cin_);
   mu = rflf(mu); kt_mode = rfl(kt_mode); kr = rflf(kr); delta_reg = rflf(delta_reg);
@@ -1837,7 +1848,7 @@ QPD void load_vectors(CT &C) {
 // Factor at the current (relaxed) point and solve the adjoint system for
 // the upstream gradient; returns dx in u0[0:n], dy in u0[n+nb:], dz in dv0.
 template <int T, int RPL, class CT>
-__device__ __noinline__ bool adjoint(CT &Cin_, bool bounded, const gf *gx, const gf *gy, const gf *gz,
+QPK_PHASE bool adjoint(CT &Cin_, bool bounded, const gf *gx, const gf *gy, const gf *gz,
                  float delta_reg, int refine_steps, double &work) {
   CT C = uctx(Cin_);
   bounded = rfl(bounded); gx = rflp(gx); gy = rflp(gy); gz = rflp(gz);
@@ -1957,7 +1968,7 @@ __device__ __noinline__ bool adjoint(CT &Cin_, bool bounded, const gf *gx, const
 
 // Write the parameter gradients of Algorithm 3 with coalesced stores.
 template <int T, class CT>
-__device__ __noinline__ void write_grads(CT &Cin_, const Params &P, size_t qi) {
+QPK_PHASE void write_grads(CT &Cin_, const Params &P, size_t qi) {
   CT C = uctx(Cin_);
   const int n = C.n, m = C.m, p = C.p, tid = threadIdx.x;
   const lf *dx = C.u0, *dy = C.u0 + n, *dz = C.dv0;
