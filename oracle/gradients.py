@@ -67,11 +67,12 @@ def grad_at_relaxed(Q, q, A, b, G, h, kappa_relax, gx, gy=None, gz=None, warm=No
     return ift_vjp(Q, q, A, b, G, h, rr.x, rr.y, rr.z, rr.s, gx, gy, gz), rr
 
 
-def fd_vjp(Q, q, A, b, G, h, kappa_relax, gx, direction, step, warm):
+def fd_vjp(Q, q, A, b, G, h, kappa_relax, gx, direction, step, warm, gy=None, gz=None):
     """Central difference (l(theta + t D) - l(theta - t D)) / 2t with
-    l = gx' x_relaxed(theta).  ``direction`` is a dict with keys Q..h (Q's
-    direction should be symmetric); ``warm`` is the relaxed point at theta,
-    used to warm-start both perturbed relaxations."""
+    l = gx' x + gy' y + gz' z at the relaxed point (gy, gz optional).
+    ``direction`` is a dict with keys Q..h (Q's direction should be
+    symmetric); ``warm`` is the relaxed point at theta, used to warm-start
+    both perturbed relaxations."""
     base = dict(Q=Q, q=q, A=A, b=b, G=G, h=h)
     vals = []
     for sgn in (1.0, -1.0):
@@ -79,5 +80,10 @@ def fd_vjp(Q, q, A, b, G, h, kappa_relax, gx, direction, step, warm):
               for k in base}
         rr = implicit.relax_qp(th["Q"], th["q"], th["A"], th["b"], th["G"], th["h"],
                                *warm, kappa_relax, tol=1e-13, max_iter=200)
-        vals.append(float(gx @ rr.x))
+        val = float(gx @ rr.x)
+        if gy is not None:
+            val += float(gy @ rr.y)
+        if gz is not None:
+            val += float(gz @ rr.z)
+        vals.append(val)
     return (vals[0] - vals[1]) / (2.0 * step)

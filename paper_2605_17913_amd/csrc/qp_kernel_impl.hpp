@@ -399,7 +399,7 @@ QPD void panel_load(const MF *M, int N, int k0, int i, float (&R)[kNB]) {
   }
 }
 template <class MF>
-QPD void panel_store(MF *M, int N, int k0, int i, const float (&R)[kNB]) {
+QPD void panel_store(MF *M, int N, int k0, int i, const float (&R)[kNB], float &lmax) {
   typedef typename Vec4<MF>::type V4;
   if (i >= N) return;
   const int r = i - k0;
@@ -412,6 +412,10 @@ QPD void panel_store(MF *M, int N, int k0, int i, const float (&R)[kNB]) {
     v4.z = (c + 2 <= r) ? R[c + 2] : 0.f;
     v4.w = (c + 3 <= r) ? R[c + 3] : 0.f;
     *reinterpret_cast<V4 *>(row + c) = v4;
+    // largest |L| written (a NaN counts as infinite)
+    const float a = fmaxf(fmaxf(fabsf(v4.x), fabsf(v4.y)), fmaxf(fabsf(v4.z), fabsf(v4.w)));
+    const bool nan = v4.x != v4.x || v4.y != v4.y || v4.z != v4.z || v4.w != v4.w;
+    lmax = nan ? __int_as_float(0x7f800000) : fmaxf(lmax, a);
   }
 }
 
@@ -432,8 +436,10 @@ QPD void panel_store(MF *M, int N, int k0, int i, const float (&R)[kNB]) {
 // rows plus equalities than unknowns) factorable in FP32.
 constexpr float kPivTol = 1e-6f;
 constexpr float kPivReg = 1e-5f;
+constexpr float kGrowthMax = 1e4f;  // accepted |L| / sqrt(largest pivot) with replacements
 template <int RPL, class MF>
-QPD bool factor_panel(MF *M, int N, int npos, int k0, bool dyn, float &pmax, int &nreg) {
+QPD bool factor_panel(MF *M, int N, int npos, int k0, bool dyn, float &pmax, int &nreg,
+                      float &lmax) {
   constexpr int GRP = RPL - 1 < 4 ? RPL - 1 : 4;
   const int lane = threadIdx.x & 63;
   const int kb = min(kNB, N - k0);
@@ -471,9 +477,9 @@ QPD bool factor_panel(MF *M, int N, int npos, int k0, bool dyn, float &pmax, int
       }
     }
   }
-  panel_store(M, N, k0, k0 + lane, P0);
+  panel_store(M, N, k0, k0 + lane, P0, lmax);
 #pragma unroll
-  for (int g = 0; g < GRP; ++g) panel_store(M, N, k0, k0 + lane + 64 * (1 + g), P[g]);
+  for (int g = 0; g < GRP; ++g) panel_store(M, N, k0, k0 + lane + 64 * (1 + g), P[g], lmax);
 #pragma unroll 1
   for (int t0 = 1 + GRP; t0 < RPL; t0 += GRP) {
     if (k0 + 64 * t0 >= N) break;
@@ -494,7 +500,7 @@ QPD bool factor_panel(MF *M, int N, int npos, int k0, bool dyn, float &pmax, int
       }
     }
 #pragma unroll
-    for (int g = 0; g < GRP; ++g) panel_store(M, N, k0, k0 + lane + 64 * (t0 + g), P[g]);
+    for (int g = 0; g < GRP; ++g) panel_store(M, N, k0, k0 + lane + 64 * (t0 + g), P[g], lmax);
   }
   return fail;
 }
@@ -515,11 +521,11 @@ QPK_PHASE bool signed_cholesky(MF *M, int N, int npos, li *flag, bool dyn) {
   M = rflp(M); N = rfl(N); npos = rfl(npos); flag = rflp(flag); dyn = rfl(dyn);
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   // wave 0's running pivot scale and count of regularised pivots
-  float pmax = 0.f;
+  float pmax = 0.f, lmax = 0.f;
   int nreg = 0;
   if (tid == 0) { flag[0] = 0; flag[2] = 0; }
   if (wid == 0) {
-    const bool fail = factor_panel<RPL>(M, N, npos, 0, dyn, pmax, nreg);
+    const bool fail = factor_panel<RPL>(M, N, npos, 0, dyn, pmax, nreg, lmax);
     if (fail && lane == 0) flag[0] = 1;
   }
   __syncthreads();
@@ -547,7 +553,7 @@ QPK_PHASE bool signed_cholesky(MF *M, int N, int npos, li *flag, bool dyn) {
     __syncthreads();
     // (2) wave 0: factor the next panel; waves 1..: rest of the update
     if (wid == 0) {
-      const bool fail = factor_panel<RPL>(M, N, npos, r0, dyn, pmax, nreg);
+      const bool fail = factor_panel<RPL>(M, N, npos, r0, dyn, pmax, nreg, lmax);
       if (fail && lane == 0) flag[0] = 1;
     } else {
       const int r1 = r0 + kNB, R1 = N - r1;
@@ -564,6 +570,14 @@ QPK_PHASE bool signed_cholesky(MF *M, int N, int npos, li *flag, bool dyn) {
       }
     }
     __syncthreads();
+  }
+  if (wid == 0) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) lmax = fmaxf(lmax, __shfl_xor(lmax, o, 64));
+    // with regularised pivots, entries of L far beyond the scale sqrt(pmax)
+    // of a stable factor mean the replaced pivots amplified rounding errors:
+    // report a failure so the caller factors again with a uniform floor
+    if (lane == 0 && nreg > 0 && !(lmax <= kGrowthMax * sqrtf(pmax))) flag[0] = 1;
   }
   if (tid == 0) {
     flag[2] = nreg;

@@ -32,7 +32,7 @@ import numpy as np
 
 __all__ = [
     "QPBatch", "random_feasible", "ill_conditioned", "projection",
-    "box_qp", "serving_requests", "upstream", "CONFIGS", "make_config",
+    "box_qp", "safety_filter", "serving_requests", "upstream", "CONFIGS", "make_config",
 ]
 
 
@@ -182,6 +182,53 @@ def box_qp(B: int, n: int, seed: int) -> QPBatch:
     return QPBatch(Q, q, A, b, G, h, extra={"d": d.astype(np.float32).astype(np.float64),
                                             "lo": -h[:, n:].astype(np.float64),
                                             "hi": h[:, :n].astype(np.float64)})
+
+
+def safety_filter(B: int, n_agents: int, seed: int) -> QPBatch:
+    """Batches shaped like the paper's multi-agent safety filter (appendix F):
+    2 N_a variables (a planar control per agent), Q = I, q = -u_nom, no
+    equalities, and 4 N_a + 3 N_a + N_a (N_a - 1) / 2 inequality rows:
+    per agent the four bounds |u_x|, |u_y| <= 1 and three half-planes
+    a' u_i <= h (unit normals a), and per pair of agents one half-plane
+    d' (u_i - u_j) <= h_ij.  The appendix trains a network to produce the
+    constraint data, which is not available; the half-planes here are
+    random, with offsets drawn so that u0 (|u0| < 0.5) is strictly feasible,
+    and u_nom ~ N(0, 1) makes a share of the rows active at the optimum."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    na = n_agents
+    n = 2 * na
+    m = 4 * na + 3 * na + na * (na - 1) // 2
+    G = np.zeros((B, m, n))
+    r = 0
+    for i in range(na):
+        for c in range(2):
+            G[:, r, 2 * i + c] = 1.0
+            G[:, r + 1, 2 * i + c] = -1.0
+            r += 2
+    for i in range(na):
+        a = rng.standard_normal((B, 3, 2))
+        a /= np.linalg.norm(a, axis=2, keepdims=True)
+        G[:, r:r + 3, 2 * i:2 * i + 2] = a
+        r += 3
+    for i in range(na):
+        for j in range(i + 1, na):
+            d = rng.standard_normal((B, 2))
+            d /= np.linalg.norm(d, axis=1, keepdims=True)
+            G[:, r, 2 * i:2 * i + 2] = d
+            G[:, r, 2 * j:2 * j + 2] = -d
+            r += 1
+    u0 = rng.uniform(-0.5, 0.5, (B, n))
+    G = _f32(G)[0]
+    gu = np.einsum("bmn,bn->bm", G.astype(np.float64), u0)
+    h = np.empty((B, m))
+    h[:, :4 * na] = 1.0
+    h[:, 4 * na:] = gu[:, 4 * na:] + rng.uniform(0.05, 1.0, (B, m - 4 * na))
+    Q = np.broadcast_to(np.eye(n), (B, n, n)).copy()
+    q = -rng.standard_normal((B, n))
+    Q, q, h = _f32(Q, q, h)
+    A = np.zeros((B, 0, n), np.float32)
+    b = np.zeros((B, 0), np.float32)
+    return QPBatch(Q, q, A, b, G, h, extra={"u0": u0})
 
 
 def upstream(B: int, n: int, seed: int) -> np.ndarray:

@@ -76,6 +76,42 @@ def test_gradients_match_central_differences(seed):
             assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (key, fd, an)
 
 
+@pytest.mark.parametrize("seed", range(2))
+def test_full_vjp_matches_central_differences(seed):
+    # upstream on all three outputs: l = gx'x + gy'y + gz'z at the relaxed
+    # point (the multipliers are unique there for kappa_relax > 0 and A of
+    # full row rank)
+    n, m, p = [(5, 8, 2), (6, 9, 1)][seed]
+    P = qpgen.random_feasible(1, n, m, p, seed=40 + seed)
+    Q, q, A, b, G, h = P.one(0)
+    rng = np.random.default_rng(100 + seed)
+    gx, gy, gz = rng.standard_normal(n), rng.standard_normal(p), rng.standard_normal(m)
+    kr = 1e-2
+    gr, rr = gradients.grad_at_relaxed(Q, q, A, b, G, h, kr, gx, gy, gz)
+    warm = (rr.x, rr.y, rr.z, rr.s)
+    for key, shape in [("Q", (n, n)), ("q", (n,)), ("A", (p, n)), ("b", (p,)),
+                       ("G", (m, n)), ("h", (m,))]:
+        D = rng.standard_normal(shape)
+        if key == "Q":
+            D = 0.5 * (D + D.T)
+        fd = gradients.fd_vjp(Q, q, A, b, G, h, kr, gx, {key: D}, 1e-5, warm, gy=gy, gz=gz)
+        an = float(np.sum(gr[key] * D))
+        assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (key, fd, an)
+
+
+def test_safety_filter_shapes_and_feasibility():
+    # appendix F shapes: 2 N_a variables, 4 N_a + 3 N_a + N_a (N_a - 1) / 2 rows
+    for na in (1, 4, 9):
+        P = qpgen.safety_filter(3, na, seed=na)
+        n, m = 2 * na, 7 * na + na * (na - 1) // 2
+        assert P.Q.shape == (3, n, n) and P.G.shape == (3, m, n) and P.A.shape == (3, 0, n)
+        u0 = P.extra["u0"]
+        slack = P.h.astype(np.float64) - np.einsum("bmn,bn->bm", P.G.astype(np.float64), u0)
+        assert np.all(slack > 0.04)
+        r = implicit.solve_qp(*P.one(0))
+        assert r.status == implicit.CONVERGED
+
+
 def test_scalar_qp_golden():
     # tests/golden/scalar_qp.json: a one-variable QP worked by hand
     import json
