@@ -90,7 +90,9 @@ typedef struct {
                             gradient of a near-degenerate QP needs a relaxed
                             point tighter than the solve's tolerance         */
   int32_t kmax;          /* cap on bordered inequality rows of the bounded
-                            factorisation; 0 = automatic (n)                  */
+                            factorisation; 0 = automatic: n when the factor
+                            fits the workgroup's LDS, else every row (up to
+                            m, within 1024 - n - p bordered-system rows)     */
   float delta_reg;       /* relative Tikhonov floor on the bordered block (0) */
   int32_t refine_steps;  /* iterative refinement steps of each KKT solve (0)  */
   int32_t block;         /* threads per QP: 0 = automatic, or 128/256/512     */

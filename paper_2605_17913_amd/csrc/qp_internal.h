@@ -113,6 +113,22 @@ inline int make_plan(int n, int m, int p, const qp_opts &o, Plan *pl) {
     pl->ws_stride = 0;
   } else {
     pl->m_in_lds = false;
+    // The factor lives in global memory anyway: with the automatic cap,
+    // border every row with v > 0 (up to m, within kMaxN), which keeps every
+    // multiplier bounded also when more than n rows are active.  This costs
+    // workspace, not LDS occupancy.
+    if (o.kmax == 0 && o.form != QPX_STANDARD) {
+      const int kb2 = std::min(m, kMaxN - n - p);
+      const int N2 = n + kb2 + p;
+      const int T2 = o.block ? o.block : (N2 <= 256 ? 256 : 512);
+      if (kb2 > kb && !(N2 > 512 && T2 != 512) &&
+          qpk::lds_bytes(n, m, p, kb2, false, T2) <= lim) {
+        kb = kb2;
+        pl->kb = kb;
+        T = T2;
+        pl->threads = T;
+      }
+    }
     pl->lds = qpk::lds_bytes(n, m, p, kb, false, T);
     if (pl->lds > lim) return QPX_ERR_UNSUPPORTED;
     pl->ws_stride = qpk::ws_floats(n, m, p, kb);

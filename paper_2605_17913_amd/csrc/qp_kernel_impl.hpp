@@ -436,7 +436,8 @@ QPD void panel_store(MF *M, int N, int k0, int i, const float (&R)[kNB], float &
 // rows plus equalities than unknowns) factorable in FP32.
 constexpr float kPivTol = 1e-6f;
 constexpr float kPivReg = 1e-5f;
-constexpr float kGrowthMax = 1e4f;  // accepted |L| / sqrt(largest pivot) with replacements
+constexpr float kGrowthMax = 1e2f;  // accepted max|L| / sqrt(largest pivot) with
+                                    // replacements (a stable factor stays near 1)
 template <int RPL, class MF>
 QPD bool factor_panel(MF *M, int N, int npos, int k0, bool dyn, float &pmax, int &nreg,
                       float &lmax) {
@@ -1385,19 +1386,38 @@ QPK_PHASE void border_delta(CT &Cin_, int nb, float rel, float floor_abs) {
   __syncthreads();
 }
 
+// True (uniformly) if a[0..N) or b[0..N) (b may be null) holds a
+// non-finite value.
+template <int T>
+QPD bool any_nonfinite(const lf *a, const lf *b, int N, lf *red) {
+  float f[1] = {0.f};
+  for (int j = threadIdx.x; j < N; j += T) {
+    if (!finitef(a[j]) || (b && !finitef(b[j]))) f[0] = 1.f;
+  }
+  block_reduce<T, OpMax, 1>(f, red);
+  return f[0] != 0.f;
+}
+
 // Assemble and factor the bounded-form matrix.  On a pivot breakdown the
 // matrix is rebuilt with a border floor and factored again; *regularised
 // tells the caller to refine against the unregularised operator.
 constexpr float kRetryReg = 1e-4f;
 template <int T, int RPL, class CT>
-QPD bool factor_bounded(CT &C, int nb, int ne, const lf *wts, float delta_rel, bool *regularised) {
+QPD bool factor_bounded(CT &C, int nb, int ne, const lf *wts, float delta_rel, bool *regularised,
+                        bool floor = false) {
   const int N = C.n + nb + C.p;
   assemble<T>(C, nb, ne, wts, true, 0.f);
-  if (delta_rel > 0.f) border_delta<T>(C, nb, delta_rel, 0.f);
+  if (floor) {
+    // asked for by a caller whose solve came out non-finite: floor the
+    // border at the scale of the previous factorisation's pivots
+    border_delta<T>(C, nb, fmaxf(delta_rel, 1e-6f), kRetryReg * __int_as_float(C.iflag[4]));
+  } else if (delta_rel > 0.f) {
+    border_delta<T>(C, nb, delta_rel, 0.f);
+  }
   QPK_PT(C, PH_ASM);
   bool ok = signed_cholesky<T, RPL>(C.M, N, C.n, C.iflag, true);
   QPK_PT(C, PH_FACT);
-  *regularised = delta_rel > 0.f || C.iflag[2] > 0;
+  *regularised = delta_rel > 0.f || floor || C.iflag[2] > 0;
   if (!ok) {
     // the floor is at least kRetryReg times the largest pivot the failed
     // attempt accepted, i.e. scaled like the Schur complement's entries
@@ -1601,13 +1621,14 @@ QPK_PHASE int newton_bounded(CT &Cin_, float &kappa, int kt_mode, float sigma, f
   // refinement that contracts by less than kRefineSlow per step means the
   // assembly error is too large for this system's conditioning: the QP
   // switches to FP32 matrix-core assembly and the step is redone.
-  bool ok = false;
-  for (int attempt = 0; attempt < 2; ++attempt) {
+  // at most one switch of the assembly arithmetic and one floored redo
+  bool ok = false, floor = false;
+  for (int attempt = 0; attempt < 3; ++attempt) {
     // weights E/D for eliminated rows (in t1 until the right-hand sides)
     for (int i = tid; i < m; i += T) C.t1[i] = C.E[i] / C.D[i];
     __syncthreads();
     bool reg = false;
-    ok = factor_bounded<T, RPL>(C, nb, ne, C.t1, delta_reg, &reg);
+    ok = factor_bounded<T, RPL>(C, nb, ne, C.t1, delta_reg, &reg, floor);
     work += (double)ne * dn * (dn + 1.0) + dN * dN * dN / 3.0;      // assembly + factor
     work += 2.0 * (2.0 * dN * dN + 4.0 * dm * dn);                  // two solves
     if (!ok) break;
@@ -1631,6 +1652,12 @@ QPK_PHASE int newton_bounded(CT &Cin_, float &kappa, int kt_mode, float sigma, f
         __syncthreads();
         continue;
       }
+    }
+    // a factor that passed its checks can still give a non-finite solution
+    // when it is nearly singular: redo the step once with a border floor
+    if (!floor && any_nonfinite<T>(C.u0, C.u1, N, C.red)) {
+      floor = true;
+      continue;
     }
     break;
   }
@@ -1843,7 +1870,14 @@ QPD int newton_loop(CT &C, bool bounded, int max_iter, float tol, int kt_mode, f
     if (bounded)
       st = newton_bounded<T, RPL>(C, kappa, kt_mode, sigma, kr, delta_reg, refine_steps, work, &stage);
     else st = newton_standard<T, RPL>(C, kappa, kt_mode, kr, delta_reg, work, &stage);
-    if (st != ST_CONV) { status = st; iters = it + 1; break; }
+    if (st != ST_CONV) {
+      status = st;
+      // a failure inside the relaxation (Algorithm 2) is attributed to it as
+      // a whole, whichever sub-step produced it
+      if (kt_mode == 2) stage = SG_RELAX;
+      iters = it + 1;
+      break;
+    }
   }
   return mkstatus(status, stage);
 }
@@ -1903,14 +1937,16 @@ QPK_PHASE bool adjoint(CT &Cin_, bool bounded, const gf *gx, const gf *gy, const
   if (bounded) {
     C.amode = rfl(C.iflag[3]);
     // as in newton_bounded: fall back from split-product assembly when the
-    // refinement does not contract
-    for (int attempt = 0; attempt < 2; ++attempt) {
+    // refinement does not contract, and floor the border when the solve is
+    // not finite
+    bool floor = false;
+    for (int attempt = 0; attempt < 3; ++attempt) {
       if (attempt) {
         for (int i = tid; i < m; i += T) C.t1[i] = C.E[i] / C.D[i];
         __syncthreads();
       }
       bool reg = false;
-      ok = factor_bounded<T, RPL>(C, nb, ne, C.t1, delta_reg, &reg);
+      ok = factor_bounded<T, RPL>(C, nb, ne, C.t1, delta_reg, &reg, floor);
       work += wfac + wref;
       if (!ok) break;
       make_dinv<T>(C, N);
@@ -1923,6 +1959,10 @@ QPK_PHASE bool adjoint(CT &Cin_, bool bounded, const gf *gx, const gf *gy, const
         C.amode = 2;
         if (tid == 0) C.iflag[3] = 2;
         __syncthreads();
+        continue;
+      }
+      if (!floor && any_nonfinite<T>(C.u0, nullptr, N, C.red)) {
+        floor = true;
         continue;
       }
       break;
