@@ -91,3 +91,51 @@ def test_ill_conditioned_degenerate():
     assert np.all(st == 0), st.tolist()
     assert max(errs) <= 1e-4, errs
     _parity(P, sol, [0], 1e-4, None)
+
+
+def test_ill_conditioned_batch_all_converge():
+    # the benchmark's 512-QP batch of the ill-conditioned shape: every QP
+    # converges and matches the planted optimum (which the FP64 oracle
+    # reproduces to 1e-7).  The scaled residual does not bound the error in
+    # x on this shape (smallest eigenvalue of Q 1e-4): at tol 1e-5, 2 of the
+    # 512 QPs are 1.6e-4 away; at 1e-6 (0.6 more iterations on average)
+    # every QP is within 2e-5, so the test asks for 1e-6.
+    P = qpgen.ill_conditioned(512, 256, 512, 32, seed=4)
+    print("ill-conditioned degenerate n=256 m=512 p=32 B=512 tol=1e-6 (default assembly)",
+          flush=True)
+    sol = _run(P, tol=1e-6)
+    st = sol["status"] & 0xFF
+    errs = np.array([_rel(sol["x"][i], P.extra["x_star"][i]) for i in range(P.B)])
+    print(f"  failed {np.nonzero(st)[0].tolist()} worst x err {errs.max():.2e}", flush=True)
+    assert np.all(st == 0), np.nonzero(st)[0].tolist()
+    assert errs.max() <= 1e-4, (int(errs.argmax()), float(errs.max()))
+
+
+def test_ill_conditioned_gradients():
+    # IFT gradients on the degenerate shape against the FP64 oracle at
+    # kappa_relax = 1e-3 (the paper's FP32 setting for its hardest workload).
+    # At 1e-4 the relaxation does not reach its tolerance within 30
+    # iterations on this shape (status MAX_ITER) and the gradient is not
+    # accurate; the status tells the caller.
+    import paper_2605_17913_amd as qpx
+    from oracle import gradients
+    d = _dev()
+    P = qpgen.ill_conditioned(2, 256, 512, 32, seed=1)
+    print("ill-conditioned gradients n=256 m=512 p=32 B=2 kappa_relax=1e-3", flush=True)
+    Q, q, A, b, G, h = [torch.from_numpy(a).to(d) for a in P.arrays()]
+    sol = qpx.solve(Q, q, A, b, G, h, tol=1e-6)
+    gx = qpgen.upstream(P.B, 256, seed=2)
+    g = qpx.backward(Q, q, A, b, G, h, sol, torch.from_numpy(gx).to(d), kappa_relax=1e-3,
+                     relaxed=True)
+    torch.cuda.synchronize()
+    # converged, or stopped at relax_max_iter just short of relax_tol (the
+    # default refinement leaves the relaxed residual near 1e-7 on this shape;
+    # refine_steps=8 converges it): the gradients are checked either way
+    assert int(g["relaxed"]["status"][0].item()) & 0xFF <= 1
+    ref, rr = gradients.grad_at_relaxed(*P.one(0), 1e-3, gx[0].astype(np.float64))
+    assert _rel(g["relaxed"]["x"][0].cpu().numpy(), rr.x) <= 1e-4
+    for key in ("Q", "q", "A", "b", "G", "h"):
+        gg = g[key][0].cpu().numpy()
+        err = np.linalg.norm(gg - ref[key]) / max(1e-3, np.linalg.norm(ref[key]))
+        print(f"  d{key} err {err:.2e}", flush=True)
+        assert err <= 1e-3, (key, err)
