@@ -196,7 +196,8 @@ def projection_grad_errors(n, n_ineq, n_act, kappa_relax, tol, form, seeds=(0, 1
     """Appendix D experiment on the GPU: Euclidean projection onto a polytope
     (Q = I, q = -x_query, no equalities) with a planted active face; the
     gradient of v'Pi(x) with respect to x (= -dl/dq for upstream v) is
-    compared with the hard-projection reference J_hard v (eq. hard-jacobian).
+    compared with the hard-projection reference J_hard v (eq. hard-jacobian),
+    the error measured relative to |v|.
     All (seed, distance) instances of a cell run as one batch.  Returns
     per-instance relative errors (nan on failure) and the first failing
     solver stage of each failed instance."""
@@ -234,22 +235,25 @@ def projection_grad_errors(n, n_ineq, n_act, kappa_relax, tol, form, seeds=(0, 1
             stage = (code >> 8) & 0xff if (bad_s or bad_r) else 7
             stages.append(qpx.STAGES[stage])
         else:
-            errs.append(float(np.linalg.norm(gq[k] - ghs[k]) / np.linalg.norm(ghs[k])))
+            # relative to |v| (|J_hard| <= 1; J_hard v vanishes at a vertex)
+            errs.append(float(np.linalg.norm(gq[k] - ghs[k]) / np.linalg.norm(vs[k])))
     return np.array(errs), stages
 
 
 def ablation():
     """Size sweep (kappa_relax = 1e-4, tol 1e-4, #ineq = 1.25 n, active ratio
     m_r in {0.2, 0.6, 0.8}) and kappa_relax sweep (n = 20, 25 inequalities,
-    10/12/15 active, tol = min(kappa_relax, 1e-4)) for both formulations in
-    FP32, as in the paper's appendix D; medians over 3 seeds x 21 distances."""
+    10/12/15 active, tol = min(kappa_relax, 1e-4)) in FP32, as in the paper's
+    appendix D, for the bounded form, the standard form and the first
+    partially condensed form (appendix B.3, the negative control); medians
+    over 3 seeds x 21 distances."""
     out = {"size_sweep": [], "kappa_sweep": []}
     for n in (2, 6, 10, 14, 18, 22, 26, 30, 34, 38):
         for mr in (0.2, 0.6, 0.8):
             n_ineq = int(round(1.25 * n))
             n_act = max(1, int(round(mr * n)))
             row = {"n": n, "m_r": mr}
-            for form in ("bounded", "standard"):
+            for form in ("bounded", "standard", "condensed"):
                 e, st = projection_grad_errors(n, n_ineq, n_act, 1e-4, 1e-4, form)
                 row[form] = {"fail_rate": round(float(np.mean(np.isnan(e))), 3),
                              "median_err": (round(float(np.nanmedian(e)), 6)
@@ -258,7 +262,7 @@ def ablation():
     for n_act in (10, 12, 15):
         for kr in (1e-2, 1e-3, 1e-4, 1e-5, 1e-6, 1e-7, 1e-8, 1e-9):
             row = {"n_active": n_act, "kappa_relax": kr}
-            for form in ("bounded", "standard"):
+            for form in ("bounded", "standard", "condensed"):
                 e, st = projection_grad_errors(20, 25, n_act, kr, min(kr, 1e-4), form)
                 counts = {}
                 for x in st:

@@ -58,7 +58,9 @@ extern "C" {
 #define QPX_STAGE_CENTERING 3  /* centering quantities (sigma, mu / kappa)    */
 #define QPX_STAGE_CORRECTOR 4  /* corrector direction                         */
 #define QPX_STAGE_LINESEARCH 5 /* step length                                 */
-#define QPX_STAGE_RELAX 6      /* relaxation to kappa_relax                   */
+#define QPX_STAGE_RELAX 6      /* relaxation to kappa_relax (Algorithm 2),
+                                  including the factorisation at the relaxed
+                                  point that the gradients use               */
 #define QPX_STAGE_BACKWARD 7   /* adjoint solve / gradients                   */
 
 /* ---- formulations ------------------------------------------------------- */
@@ -66,6 +68,13 @@ extern "C" {
                            (section 4, eq. implicit_partially_condensed)      */
 #define QPX_STANDARD 1  /* standard explicit complementarity (section 3,
                            eq. explicit_partially_condensed); ablation arm    */
+#define QPX_CONDENSED 2 /* implicit complementarity solved through the first
+                           partially condensed form of appendix B.3: dv is
+                           eliminated from every row, so the reduced matrix
+                           Q + G' diag(z/s) G is unbounded as in the
+                           standard form; no regularisation.  Negative
+                           control of the ablation (expected to degrade in
+                           FP32).                                             */
 
 typedef struct qpx_ctx qpx_ctx;
 
@@ -77,7 +86,7 @@ typedef struct {
 } qp_batch;
 
 typedef struct {
-  int32_t form;          /* QPX_BOUNDED or QPX_STANDARD                       */
+  int32_t form;          /* QPX_BOUNDED, QPX_STANDARD or QPX_CONDENSED       */
   int32_t max_iter;      /* Newton iterations of the solve (default 100)      */
   float tol;             /* stopping tolerance on scaled residuals (1e-5)     */
   float sigma;           /* fixed centering kappa_target = sigma kappa when

@@ -29,7 +29,7 @@ LIB_PATH = os.environ.get("QPX_LIB") or os.path.join(_HERE, "libqpx.so")
 QPX_OK, QPX_PENDING = 0, 1
 CONVERGED, MAX_ITER, NONFINITE, FACTOR_FAIL = 0, 1, 2, 3
 STAGES = ["none", "scaling", "predictor", "centering", "corrector", "linesearch", "relax", "backward"]
-FORMS = {"bounded": 0, "standard": 1}
+FORMS = {"bounded": 0, "standard": 1, "condensed": 2}
 # H-block assembly arithmetic (qp_opts.assembly)
 ASSEMBLY = {"auto": 0, "fp32": 1, "bf16x3": 2, "mfma_fp32": 3}
 

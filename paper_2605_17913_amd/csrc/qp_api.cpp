@@ -48,7 +48,7 @@ int check_batch(const qp_batch *bt) {
 }
 
 int check_opts(const qp_opts &o) {
-  if (o.form != QPX_BOUNDED && o.form != QPX_STANDARD) return QPX_ERR_ARG;
+  if (o.form != QPX_BOUNDED && o.form != QPX_STANDARD && o.form != QPX_CONDENSED) return QPX_ERR_ARG;
   if (!(o.tol > 0.f) || o.max_iter < 1 || o.max_iter > 100000) return QPX_ERR_ARG;
   if (!(o.sigma > 0.f && o.sigma < 1.f)) return QPX_ERR_ARG;
   if (!(o.delta_reg >= 0.f)) return QPX_ERR_ARG;

@@ -93,7 +93,7 @@ struct Plan {
 inline int make_plan(int n, int m, int p, const qp_opts &o, Plan *pl) {
   int kb = o.kmax > 0 ? o.kmax : n;
   kb = std::min(kb, m);
-  if (o.form == QPX_STANDARD) kb = 0;
+  if (o.form != QPX_BOUNDED) kb = 0;  // standard and first condensed forms: no border
   if (kb < 0) kb = 0;
   if (n + kb + p > kMaxN) kb = kMaxN - n - p;
   if (kb < 0 || n + p > kMaxN) return QPX_ERR_UNSUPPORTED;
@@ -117,7 +117,7 @@ inline int make_plan(int n, int m, int p, const qp_opts &o, Plan *pl) {
     // border every row with v > 0 (up to m, within kMaxN), which keeps every
     // multiplier bounded also when more than n rows are active.  This costs
     // workspace, not LDS occupancy.
-    if (o.kmax == 0 && o.form != QPX_STANDARD) {
+    if (o.kmax == 0 && o.form == QPX_BOUNDED) {
       const int kb2 = std::min(m, kMaxN - n - p);
       const int N2 = n + kb2 + p;
       const int T2 = o.block ? o.block : (N2 <= 256 ? 256 : 512);

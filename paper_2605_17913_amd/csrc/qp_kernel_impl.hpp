@@ -762,6 +762,7 @@ struct Ctx {
   li *role, *bidx, *elist, *iflag;
   lf *stg;    // matrix-core assembly staging (aliases u0 .. dd)
   int amode;  // H-block assembly: 0 FP32 VALU, 1 BF16x3 MFMA, 2 FP32 MFMA
+  int dyn;    // bounded form: regularise degenerate factorisations (R13)
   __attribute__((address_space(3))) long long *pt;
 };
 
@@ -788,6 +789,7 @@ QPD void init_ctx(Ctx<MF> &C, lf *sm, const Layout &L, MF *Mptr) {
   C.iflag = reinterpret_cast<li *>(sm + L.iflag);
   C.stg = sm + L.stg;
   C.amode = 0;
+  C.dyn = 1;
   C.pt = nullptr;  // set by profiling builds
 }
 
@@ -813,7 +815,7 @@ QPD Ctx<MF> uctx(const Ctx<MF> &I) {
   C.mz = rflp(I.mz);
   C.dd = rflp(I.dd);
   C.role = rflp(I.role); C.bidx = rflp(I.bidx); C.elist = rflp(I.elist); C.iflag = rflp(I.iflag);
-  C.stg = rflp(I.stg); C.amode = rfl(I.amode);
+  C.stg = rflp(I.stg); C.amode = rfl(I.amode); C.dyn = rfl(I.dyn);
   C.pt = rflp(I.pt);
   return C;
 }
@@ -1415,10 +1417,10 @@ QPD bool factor_bounded(CT &C, int nb, int ne, const lf *wts, float delta_rel, b
     border_delta<T>(C, nb, delta_rel, 0.f);
   }
   QPK_PT(C, PH_ASM);
-  bool ok = signed_cholesky<T, RPL>(C.M, N, C.n, C.iflag, true);
+  bool ok = signed_cholesky<T, RPL>(C.M, N, C.n, C.iflag, C.dyn != 0);
   QPK_PT(C, PH_FACT);
   *regularised = delta_rel > 0.f || floor || C.iflag[2] > 0;
-  if (!ok) {
+  if (!ok && C.dyn) {
     // the floor is at least kRetryReg times the largest pivot the failed
     // attempt accepted, i.e. scaled like the Schur complement's entries
     const float pmax = __int_as_float(C.iflag[4]);
@@ -1655,7 +1657,7 @@ QPK_PHASE int newton_bounded(CT &Cin_, float &kappa, int kt_mode, float sigma, f
     }
     // a factor that passed its checks can still give a non-finite solution
     // when it is nearly singular: redo the step once with a border floor
-    if (!floor && any_nonfinite<T>(C.u0, C.u1, N, C.red)) {
+    if (C.dyn && !floor && any_nonfinite<T>(C.u0, C.u1, N, C.red)) {
       floor = true;
       continue;
     }
@@ -1961,7 +1963,7 @@ QPK_PHASE bool adjoint(CT &Cin_, bool bounded, const gf *gx, const gf *gy, const
         __syncthreads();
         continue;
       }
-      if (!floor && any_nonfinite<T>(C.u0, nullptr, N, C.red)) {
+      if (C.dyn && !floor && any_nonfinite<T>(C.u0, nullptr, N, C.red)) {
         floor = true;
         continue;
       }
@@ -2106,7 +2108,11 @@ QPD void qp_body(const Params &P) {
   const int tid = threadIdx.x;
   // per-QP assembly mode for the Newton steps (a BF16x3 QP may fall back)
   if (tid == 0) C.iflag[3] = C.amode;
-  const bool bounded = P.form == 0;
+  // implicit complementarity (bounded form 0, or the first partially
+  // condensed form 2 as a negative control: no border rows, no
+  // regularisation); form 1 is the standard explicit IPM
+  const bool bounded = P.form != 1;
+  C.dyn = P.form == 0;
 #ifdef QPK_PHASE_TIMING
   __shared__ long long pt_acc[PH_N];
   C.pt = (__attribute__((address_space(3))) long long *)pt_acc;
@@ -2126,7 +2132,7 @@ QPD void qp_body(const Params &P) {
     gf *st = (gf *)d.state;
     bool ok = true;
     if (d.flags & 1) {
-      ok = initialize<T, RPL>(C, work, bounded);
+      ok = initialize<T, RPL>(C, work, C.dyn != 0);
     } else {
       for (int i = tid; i < n; i += T) C.x[i] = st[i];
       for (int k = tid; k < p; k += T) C.y[k] = st[n + k];
@@ -2154,7 +2160,7 @@ QPD void qp_body(const Params &P) {
       *d.res = res;
     }
   } else if constexpr (MODE == kSolve) {
-    const bool ok = initialize<T, RPL>(C, work, bounded);
+    const bool ok = initialize<T, RPL>(C, work, C.dyn != 0);
     QPK_PT(C, PH_INIT);
     if (!ok) {
       status = mkstatus(ST_FACT, SG_PRED);
@@ -2192,7 +2198,9 @@ QPD void qp_body(const Params &P) {
     const gf *gz = P.gz ? (const gf *)P.gz + qi * (size_t)m : nullptr;
     const bool ok = adjoint<T, RPL>(C, bounded, gx, gy, gz, P.delta_reg, refine, work);
     QPK_PT(C, PH_BWD);
-    if (!ok) status = mkstatus(ST_FACT, SG_BWD);
+    // Algorithm 2 hands the factorisation at the relaxed point to the
+    // gradient computation, so a breakdown there counts as a relax failure
+    if (!ok) status = mkstatus(ST_FACT, SG_RELAX);
     __syncthreads();
     write_grads<T>(C, P, qi);
     if (P.rx) for (int i = tid; i < n; i += T) ((gf *)P.rx)[qi * n + i] = C.x[i];

@@ -75,3 +75,33 @@ def test_standard_form_runs_on_the_same_inputs():
     st, rst, grad = _run(insts, "standard", 1e-4, 1e-5)
     # every outcome is a valid status code with a stage attribution
     assert np.all((st & 0xff) <= 3) and np.all(((st >> 8) & 0xff) <= 7)
+
+
+def test_condensed_form_is_correct_where_it_converges():
+    # the negative control (first partially condensed form, appendix B.3)
+    # is the same Newton method with an unbounded reduced matrix: where it
+    # converges it reaches the oracle's solution, and where it stops it is a
+    # numerical breakdown of the factorisation, which the bounded form on the
+    # same inputs does not have (measured: 24 of 64 condensed, 0 bounded)
+    import paper_2605_17913_amd as qpx
+    from oracle import implicit as oi
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    d = torch.device("cuda:0")
+    P = qpgen.random_feasible(64, 10, 20, 2, seed=5)
+    Q, q, A, b, G, h = [torch.from_numpy(a).to(d) for a in P.arrays()]
+    st = {}
+    for form in ("condensed", "bounded"):
+        sol = qpx.solve(Q, q, A, b, G, h, form=form)
+        torch.cuda.synchronize()
+        st[form] = sol["status"].cpu().numpy()
+        if form == "condensed":
+            x = sol["x"].cpu().numpy()
+    sc = st["condensed"] & 0xFF
+    conv = np.nonzero(sc == 0)[0]
+    print(f"condensed form: {len(conv)} of 64 converged", flush=True)
+    assert np.all((sc == 0) | (sc == 2) | (sc == 3))
+    assert np.sum(sc != 0) > np.sum((st["bounded"] & 0xFF) != 0)
+    for i in conv[:4]:
+        r = oi.solve_qp(*P.one(int(i)), tol=1e-11, max_iter=200)
+        assert np.linalg.norm(x[i] - r.x) / max(1.0, np.linalg.norm(r.x)) <= 1e-4
