@@ -190,7 +190,9 @@ typedef struct qpx_server qpx_server;
 
 typedef struct {
   int32_t max_slots;       /* QPs resident on the device at once (256)        */
-  int32_t iters_per_step;  /* Newton iterations per device step (4)           */
+  int32_t iters_per_step;  /* Newton iterations per device step for the
+                              largest size classes (4); systems of at most
+                              64 / 128 rows run 4x / 2x as many             */
   int32_t n_max;           /* largest n accepted (256)                        */
   size_t arena_bytes;      /* device arena for resident QPs; admission is by
                               footprint (0 = 256 MiB)                          */

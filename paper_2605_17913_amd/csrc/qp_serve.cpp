@@ -125,6 +125,12 @@ struct qpx_server {
   qp_server_opts o{};
   qp_opts so{};
   hipStream_t stream = nullptr;
+  // size-class buckets of one device step run concurrently on the main
+  // stream and these (all at the default priority); events order them after
+  // the descriptor upload and before the status download
+  static constexpr int kSide = 3;
+  hipStream_t side[kSide] = {};
+  hipEvent_t ev_ready = nullptr, ev_done[kSide] = {};
   char *arena_dev = nullptr;
   Arena arena;
   qpk::SlotDesc *d_desc = nullptr, *h_desc = nullptr;
@@ -212,22 +218,54 @@ void scheduler(qpx_server *S) {
     }
     (void)hipMemcpyAsync(S->d_desc, S->h_desc, order.size() * sizeof(qpk::SlotDesc),
                          hipMemcpyHostToDevice, S->stream);
+    // one launch per bucket; the buckets, largest estimated cost first, are
+    // dealt to the main and side streams so a step lasts about as long as
+    // its most expensive bucket rather than the sum of all of them
+    struct Launch { Bucket b; int k0, cnt; size_t lds; double cost; };
+    std::vector<Launch> launches;
     int k0 = 0;
     for (auto &g : groups) {
-      const Bucket &b = g.first;
       const int cnt = (int)g.second.size();
       size_t lds = 0;
-      for (int idx : g.second) lds = std::max(lds, S->active[idx]->plan.lds);
+      double cost = 0.0;
+      for (int idx : g.second) {
+        const Request *r = S->active[idx];
+        lds = std::max(lds, r->plan.lds);
+        const double N = r->n + r->plan.kb + r->p;
+        cost += N * N * N;
+      }
+      launches.push_back(Launch{g.first, k0, cnt, lds, cost});
+      k0 += cnt;
+    }
+    std::sort(launches.begin(), launches.end(),
+              [](const Launch &a, const Launch &b) { return a.cost > b.cost; });
+    const int nstreams = 1 + S->kSide;
+    bool used[1 + qpx_server::kSide] = {};
+    (void)hipEventRecord(S->ev_ready, S->stream);
+    for (size_t j = 0; j < launches.size(); ++j) {
+      const Launch &L = launches[j];
+      const int si = (int)(j % nstreams);
+      hipStream_t st = si == 0 ? S->stream : S->side[si - 1];
+      if (si > 0 && !used[si]) (void)hipStreamWaitEvent(st, S->ev_ready, 0);
+      used[si] = true;
       qpk::Params P;
       std::memset(&P, 0, sizeof(P));
-      P.n = 64 * b.rpl;  // dispatch only: rows-per-lane variant
-      P.form = S->so.form; P.max_iter = S->o.iters_per_step; P.pc = S->so.pc;
+      P.n = 64 * L.b.rpl;  // dispatch only: rows-per-lane variant
+      // small size classes run more iterations per step (their launches end
+      // well before the largest class's); the iterate persists between
+      // steps, so how iterations are split over steps does not change them
+      const int mult = L.b.rpl <= 1 ? 4 : (L.b.rpl <= 2 ? 2 : 1);
+      P.form = S->so.form; P.max_iter = S->o.iters_per_step * mult; P.pc = S->so.pc;
       P.tol = S->so.tol; P.sigma = S->so.sigma; P.delta_reg = S->so.delta_reg;
       P.refine = S->so.refine_steps;
-      P.desc = S->d_desc + k0;
+      P.desc = S->d_desc + L.k0;
       P.mode = qpk::kServe;
-      if (qpk::launch(P, b.threads, b.mlds, lds, cnt, S->stream) != hipSuccess) S->error = QPX_ERR_HIP;
-      k0 += cnt;
+      if (qpk::launch(P, L.b.threads, L.b.mlds, L.lds, L.cnt, st) != hipSuccess) S->error = QPX_ERR_HIP;
+    }
+    for (int si = 1; si < nstreams; ++si) {
+      if (!used[si]) continue;
+      (void)hipEventRecord(S->ev_done[si - 1], S->side[si - 1]);
+      (void)hipStreamWaitEvent(S->stream, S->ev_done[si - 1], 0);
     }
     const size_t na = order.size();
     (void)hipMemcpyAsync(S->h_status, S->d_status, na * 4, hipMemcpyDeviceToHost, S->stream);
@@ -295,6 +333,11 @@ int qp_server_create(qpx_ctx *ctx, const qp_server_opts *opts, const qp_opts *so
   }
   if (hipSetDevice(ctx->device) != hipSuccess) { delete S; return QPX_ERR_HIP; }
   bool ok = hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) == hipSuccess;
+  for (int i = 0; i < qpx_server::kSide; ++i) {
+    ok = ok && hipStreamCreateWithFlags(&S->side[i], hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&S->ev_done[i], hipEventDisableTiming) == hipSuccess;
+  }
+  ok = ok && hipEventCreateWithFlags(&S->ev_ready, hipEventDisableTiming) == hipSuccess;
   ok = ok && hipMalloc(&S->arena_dev, S->o.arena_bytes) == hipSuccess;
   const size_t ns = S->o.max_slots;
   ok = ok && hipMalloc(&S->d_desc, ns * sizeof(qpk::SlotDesc)) == hipSuccess;
@@ -401,6 +444,8 @@ int qp_server_destroy(qpx_server *S) {
   S->cv.notify_all();
   if (S->th.joinable()) S->th.join();
   if (S->stream) (void)hipStreamSynchronize(S->stream);
+  for (int i = 0; i < qpx_server::kSide; ++i)
+    if (S->side[i]) (void)hipStreamSynchronize(S->side[i]);
   for (auto &kv : S->by_ticket) delete kv.second;
   if (S->arena_dev) (void)hipFree(S->arena_dev);
   if (S->d_desc) (void)hipFree(S->d_desc);
@@ -411,6 +456,11 @@ int qp_server_destroy(qpx_server *S) {
   if (S->h_status) (void)hipHostFree(S->h_status);
   if (S->h_iters) (void)hipHostFree(S->h_iters);
   if (S->h_res) (void)hipHostFree(S->h_res);
+  for (int i = 0; i < qpx_server::kSide; ++i) {
+    if (S->ev_done[i]) (void)hipEventDestroy(S->ev_done[i]);
+    if (S->side[i]) (void)hipStreamDestroy(S->side[i]);
+  }
+  if (S->ev_ready) (void)hipEventDestroy(S->ev_ready);
   if (S->stream) (void)hipStreamDestroy(S->stream);
   delete S;
   return QPX_OK;
