@@ -188,6 +188,15 @@ __host__ __device__ inline int moff(int i) {
   return 20 * i + 16 * (8 * q * (q - 1) + q * rem);
 }
 
+// Lower-triangular tile t -> (ti, tj), tj <= ti, in row order.
+QPD void tile_ij(int t, int &ti, int &tj) {
+  int i = (int)((sqrtf(8.f * (float)t + 1.f) - 1.f) * 0.5f);
+  while ((i + 1) * (i + 2) / 2 <= t) ++i;
+  while (i * (i + 1) / 2 > t) --i;
+  ti = i;
+  tj = t - i * (i + 1) / 2;
+}
+
 // ---------------------------------------------------------------------------
 // Per-QP LDS layout (floats; ints share the float arena).  All blocks are
 // 4-float aligned.
@@ -381,6 +390,38 @@ QPD void rank16_tile(MF *M, int N, int npos, int p0, int i0, int j0) {
   }
 }
 
+// One 16x16 tile of the rank-16 update on the matrix cores, by a whole wave:
+// M[i][j] -= sum_c L[i][p0+c] sg_c L[j][p0+c] for i in block bi, j in block
+// bj (16-row blocks), j <= i.  Lane l loads the 16-byte segment
+// c = 4(l/16) .. 4(l/16)+3 of rows 16 bi + l%16 (A) and 16 bj + l%16 (B);
+// instruction q multiplies component q, so the four v_mfma_f32_16x16x4_f32
+// cover c = 0..15.  Register r of lane l holds row 4(l/16) + r, column l%16.
+// Rows at or beyond N read row N-1 and their results are dropped.
+template <class MF>
+QPD void rank16_tile16(MF *M, int N, int npos, int p0, int bi, int bj) {
+  typedef typename Vec4<const MF>::type CV4;
+  const int lane = threadIdx.x & 63, g = lane >> 4, c16 = lane & 15;
+  const int ia = min(16 * bi + c16, N - 1), jb = min(16 * bj + c16, N - 1);
+  const f4v a = *reinterpret_cast<CV4 *>(M + moff(ia) + p0 + 4 * g);
+  f4v b = *reinterpret_cast<CV4 *>(M + moff(jb) + p0 + 4 * g);
+  const int c0 = p0 + 4 * g;
+  b.x *= c0 + 0 < npos ? 1.f : -1.f;
+  b.y *= c0 + 1 < npos ? 1.f : -1.f;
+  b.z *= c0 + 2 < npos ? 1.f : -1.f;
+  b.w *= c0 + 3 < npos ? 1.f : -1.f;
+  f4v acc = {0.f, 0.f, 0.f, 0.f};
+  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b.z, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b.w, acc, 0, 0, 0);
+  const int j = 16 * bj + c16;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = 16 * bi + 4 * g + r;
+    if (i < N && j <= i) M[moff(i) + j] -= acc[r];
+  }
+}
+
 // One row's 16-column panel segment M[i][k0 .. k0+15] into registers (zeros
 // for rows at or beyond N), and back with exact zeros right of the diagonal
 // (r = i - k0 is the row's position in the panel).
@@ -534,7 +575,11 @@ QPK_PHASE bool signed_cholesky(MF *M, int N, int npos, li *flag, bool dyn) {
   for (int k0 = 0; k0 + kNB < N; k0 += kNB) {
     const int r0 = k0 + kNB, R = N - r0;
     // (1) apply panel k0 to the next panel's columns [r0, r0+16)
-    {
+    if constexpr (RPL >= 4) {
+      // 16x16 tiles on the matrix cores, one wave per tile
+      const int nbl = (R + 15) >> 4;
+      for (int t = wid; t < nbl; t += T / 64) rank16_tile16(M, N, npos, k0, (r0 >> 4) + t, r0 >> 4);
+    } else {
       const int ntr = (R + 3) >> 2;                       // tile rows
       const int nla = ntr <= 4 ? ntr * (ntr + 1) / 2 : 10 + 4 * (ntr - 4);
       for (int t = tid; t < nla; t += T) {
@@ -556,6 +601,17 @@ QPK_PHASE bool signed_cholesky(MF *M, int N, int npos, li *flag, bool dyn) {
     if (wid == 0) {
       const bool fail = factor_panel<RPL>(M, N, npos, r0, dyn, pmax, nreg, lmax);
       if (fail && lane == 0) flag[0] = 1;
+    } else if constexpr (RPL >= 4) {
+      const int r1 = r0 + kNB, R1 = N - r1;
+      if (R1 > 0) {
+        const int nbl = (R1 + 15) >> 4;
+        const int ntiles = nbl * (nbl + 1) / 2;
+        for (int t = wid - 1; t < ntiles; t += T / 64 - 1) {
+          int ti, tj;
+          tile_ij(t, ti, tj);
+          rank16_tile16(M, N, npos, k0, (r1 >> 4) + ti, (r1 >> 4) + tj);
+        }
+      }
     } else {
       const int r1 = r0 + kNB, R1 = N - r1;
       if (R1 > 0) {
@@ -1041,15 +1097,6 @@ QPD unsigned bf16_pair(float a, float b) {
 
 // LDS floats the matrix-core assembly stages for n columns.
 __host__ __device__ inline int stage_floats(int n) { return ((n + 15) & ~15) * kStgRec; }
-
-// Lower-triangular tile t -> (ti, tj), tj <= ti, in row order.
-QPD void tile_ij(int t, int &ti, int &tj) {
-  int i = (int)((sqrtf(8.f * (float)t + 1.f) - 1.f) * 0.5f);
-  while ((i + 1) * (i + 2) / 2 <= t) ++i;
-  while (i * (i + 1) / 2 > t) --i;
-  ti = i;
-  tj = t - i * (i + 1) / 2;
-}
 
 template <int T, class CT>
 QPD void assemble_h_mfma(CT &C, int ne, const lf *wts) {
