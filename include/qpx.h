@@ -111,9 +111,10 @@ typedef struct {
 
 /* Assembly of the (1,1) block of the reduced KKT matrix.  The factorisation,
  * solves and residuals are FP32 (FP64-accumulated residuals) in every mode.
- *  QPX_ASM_AUTO    QPX_ASM_MFMA_FP32 for the bounded form when n >= 128 and
+ *  QPX_ASM_AUTO    QPX_ASM_MFMA_FP32 for the bounded form when n >= 96 and
  *                  the staging buffer fits the workgroup's LDS, else
- *                  QPX_ASM_FP32 (the fastest of the three at those sizes).
+ *                  QPX_ASM_FP32 (measured: the fastest choice on each side
+ *                  of that size).
  *  QPX_ASM_FP32    FP32 fused multiply-adds on the vector ALUs.
  *  QPX_ASM_BF16X3  matrix cores: each operand split into two bfloat16 terms,
  *                  three products per pair accumulated in FP32 (relative

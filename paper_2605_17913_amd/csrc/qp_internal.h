@@ -136,7 +136,7 @@ inline int make_plan(int n, int m, int p, const qp_opts &o, Plan *pl) {
   const bool fits = qpk::mfma_stage_fits(n, m, p, kb, pl->m_in_lds, T);
   int am = o.assembly;
   if (am == QPX_ASM_AUTO)
-    am = (o.form == QPX_BOUNDED && n >= 128 && fits) ? QPX_ASM_MFMA_FP32 : QPX_ASM_FP32;
+    am = (o.form == QPX_BOUNDED && n >= 96 && fits) ? QPX_ASM_MFMA_FP32 : QPX_ASM_FP32;
   else if (am != QPX_ASM_FP32 && !fits)
     return QPX_ERR_UNSUPPORTED;
   pl->amode = am == QPX_ASM_BF16X3 ? 1 : (am == QPX_ASM_MFMA_FP32 ? 2 : 0);

@@ -324,72 +324,6 @@ QPD void coldot(const RF *R, int ld, int rows, int cols, const lf *const (&x)[NV
   }
 }
 
-// In-place M = L diag(sg) L' (lower triangle, row-major, leading dim ld),
-// sg_j = +1 for j < npos, -1 otherwise.  Blocked right-looking: one wave
-// factors each NB-wide panel in registers (lane = row), then the whole
-// workgroup applies the rank-NB update to the trailing lower triangle in
-// 4x4 register tiles.  The strict upper triangle receives a copy of L'
-// (M[j][i] = L[i][j]) so both triangular solves walk contiguous rows.
-// Returns false (uniformly) if a pivot sg_j * a_jj is not a positive
-// finite number.  RPL = rows per lane, >= ceil(N / 64).
-// One 4x4 tile of the rank-16 update M[i][j] -= sum_c L[i][p0+c] sg L[j][p0+c]
-// for i in [i0, i0+4), j in [j0, j0+4), j <= i, with the panel starting at
-// column p0 (16-byte row-segment loads).
-template <class MF>
-QPD void rank16_tile(MF *M, int N, int npos, int p0, int i0, int j0) {
-  typedef typename Vec4<const MF>::type CV4;
-  int oi[4], oj[4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    oi[a] = moff(min(i0 + a, N - 1));
-    oj[a] = moff(min(j0 + a, N - 1));
-  }
-  float acc[4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int bq = 0; bq < 4; ++bq) acc[a][bq] = 0.f;
-#pragma unroll 1
-  for (int c = 0; c < kNB; c += 4) {
-    f4v av[4], bv[4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      av[a] = *reinterpret_cast<CV4 *>(M + oi[a] + p0 + c);
-      bv[a] = *reinterpret_cast<CV4 *>(M + oj[a] + p0 + c);
-    }
-    const float s0 = (p0 + c + 0) < npos ? 1.f : -1.f;
-    const float s1 = (p0 + c + 1) < npos ? 1.f : -1.f;
-    const float s2 = (p0 + c + 2) < npos ? 1.f : -1.f;
-    const float s3 = (p0 + c + 3) < npos ? 1.f : -1.f;
-#pragma unroll
-    for (int bq = 0; bq < 4; ++bq) {
-      bv[bq].x *= s0; bv[bq].y *= s1; bv[bq].z *= s2; bv[bq].w *= s3;
-    }
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int bq = 0; bq < 4; ++bq) {
-        float r = acc[a][bq];
-        r = fmaf(av[a].x, bv[bq].x, r);
-        r = fmaf(av[a].y, bv[bq].y, r);
-        r = fmaf(av[a].z, bv[bq].z, r);
-        r = fmaf(av[a].w, bv[bq].w, r);
-        acc[a][bq] = r;
-      }
-  }
-#pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const int i = i0 + a;
-    if (i < N) {
-#pragma unroll
-      for (int bq = 0; bq < 4; ++bq) {
-        const int j = j0 + bq;
-        if (j <= i) M[oi[a] + j] -= acc[a][bq];
-      }
-    }
-  }
-}
-
 // One 16x16 tile of the rank-16 update on the matrix cores, by a whole wave:
 // M[i][j] -= sum_c L[i][p0+c] sg_c L[j][p0+c] for i in block bi, j in block
 // bj (16-row blocks), j <= i.  Lane l loads the 16-byte segment
@@ -552,6 +486,7 @@ QPD bool factor_panel(MF *M, int N, int npos, int k0, bool dyn, float &pmax, int
 // panel of lookahead: after panel k is factored, all waves first apply it
 // to the next panel's 16 columns; then wave 0 factors the next panel while
 // the other waves apply panel k to the rest of the trailing matrix.  The
+// updates run on the matrix cores in 16x16 tiles (rank16_tile16).  The
 // strict upper part of each row's last 16-column segment is left at exact
 // zeros.  Returns false (uniformly) if a pivot sg_j * a_jj is not a positive
 // finite number.  With dyn, numerically zero pivots are regularised (see
@@ -574,34 +509,18 @@ QPK_PHASE bool signed_cholesky(MF *M, int N, int npos, li *flag, bool dyn) {
 #pragma unroll 1
   for (int k0 = 0; k0 + kNB < N; k0 += kNB) {
     const int r0 = k0 + kNB, R = N - r0;
-    // (1) apply panel k0 to the next panel's columns [r0, r0+16)
-    if constexpr (RPL >= 4) {
-      // 16x16 tiles on the matrix cores, one wave per tile
+    // (1) apply panel k0 to the next panel's columns [r0, r0+16): 16x16
+    // tiles on the matrix cores, one wave per tile
+    {
       const int nbl = (R + 15) >> 4;
       for (int t = wid; t < nbl; t += T / 64) rank16_tile16(M, N, npos, k0, (r0 >> 4) + t, r0 >> 4);
-    } else {
-      const int ntr = (R + 3) >> 2;                       // tile rows
-      const int nla = ntr <= 4 ? ntr * (ntr + 1) / 2 : 10 + 4 * (ntr - 4);
-      for (int t = tid; t < nla; t += T) {
-        int ti, tj;
-        if (t < 10) {
-          ti = (int)((sqrtf(8.f * (float)t + 1.f) - 1.f) * 0.5f);
-          while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
-          while (ti * (ti + 1) / 2 > t) --ti;
-          tj = t - ti * (ti + 1) / 2;
-        } else {
-          ti = 4 + (t - 10) / 4;
-          tj = (t - 10) & 3;
-        }
-        rank16_tile(M, N, npos, k0, r0 + 4 * ti, r0 + 4 * tj);
-      }
     }
     __syncthreads();
     // (2) wave 0: factor the next panel; waves 1..: rest of the update
     if (wid == 0) {
       const bool fail = factor_panel<RPL>(M, N, npos, r0, dyn, pmax, nreg, lmax);
       if (fail && lane == 0) flag[0] = 1;
-    } else if constexpr (RPL >= 4) {
+    } else {
       const int r1 = r0 + kNB, R1 = N - r1;
       if (R1 > 0) {
         const int nbl = (R1 + 15) >> 4;
@@ -610,19 +529,6 @@ QPK_PHASE bool signed_cholesky(MF *M, int N, int npos, li *flag, bool dyn) {
           int ti, tj;
           tile_ij(t, ti, tj);
           rank16_tile16(M, N, npos, k0, (r1 >> 4) + ti, (r1 >> 4) + tj);
-        }
-      }
-    } else {
-      const int r1 = r0 + kNB, R1 = N - r1;
-      if (R1 > 0) {
-        const int nt = (R1 + 3) >> 2;
-        const int ntiles = nt * (nt + 1) / 2;
-        for (int t = tid - 64; t < ntiles; t += T - 64) {
-          int ti = (int)((sqrtf(8.f * (float)t + 1.f) - 1.f) * 0.5f);
-          while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
-          while (ti * (ti + 1) / 2 > t) --ti;
-          const int tj = t - ti * (ti + 1) / 2;
-          rank16_tile(M, N, npos, k0, r1 + 4 * ti, r1 + 4 * tj);
         }
       }
     }
