@@ -186,6 +186,24 @@ int qp_backward(qpx_ctx *ctx, const qp_batch *batch, const qp_opts *opts,
 /* Human-readable name of a per-QP status value or return code. */
 const char *qp_status_string(int code);
 
+/* Launch plan the library uses for one problem size (host only; no device
+ * call, so it also answers on a machine without a GPU). */
+typedef struct {
+  int32_t threads;         /* threads per QP (one workgroup per QP)           */
+  int32_t kb;              /* cap on bordered inequality rows                 */
+  int32_t factor_in_lds;   /* 1: the factor lives in LDS; 0: in the context's
+                              global workspace                                */
+  int32_t assembly;        /* QPX_ASM_FP32, QPX_ASM_BF16X3 or QPX_ASM_MFMA_FP32 */
+  size_t lds_bytes;        /* dynamic LDS per workgroup                       */
+  size_t workspace_bytes;  /* global factor workspace per QP (0 if in LDS)   */
+} qp_plan;
+
+/* Fill *plan for n, m, p under opts (NULL = defaults).  Returns QPX_OK,
+ * QPX_ERR_ARG (invalid sizes or options) or QPX_ERR_UNSUPPORTED (sizes the
+ * kernels do not handle: bordered system above 1024 rows, m above 4096, or
+ * an explicit matrix-core assembly whose staging does not fit). */
+int qp_plan_query(int32_t n, int32_t m, int32_t p, const qp_opts *opts, qp_plan *plan);
+
 /* ---- serving: continuous batching of single QPs ------------------------- */
 typedef struct qpx_server qpx_server;
 

@@ -68,8 +68,14 @@ class _Timing(ctypes.Structure):
                 ("t_done", ctypes.c_double), ("status", _c_int32), ("iters", _c_int32)]
 
 
+class _Plan(ctypes.Structure):
+    _fields_ = [("threads", _c_int32), ("kb", _c_int32), ("factor_in_lds", _c_int32),
+                ("assembly", _c_int32), ("lds_bytes", ctypes.c_size_t),
+                ("workspace_bytes", ctypes.c_size_t)]
+
+
 EXPORTS = ["qp_default_opts", "qp_create", "qp_destroy", "qp_solve", "qp_backward",
-           "qp_status_string", "qp_server_create", "qp_serve_submit", "qp_serve_poll",
+           "qp_status_string", "qp_plan_query", "qp_server_create", "qp_serve_submit", "qp_serve_poll",
            "qp_serve_stats", "qp_server_destroy"]
 
 _lib = None
@@ -94,6 +100,8 @@ def lib() -> ctypes.CDLL:
                                       ctypes.POINTER(_Out), _vp, _vp, _vp,
                                       ctypes.POINTER(_Grads), ctypes.POINTER(_Out), _vp]
             L.qp_status_string.restype = ctypes.c_char_p
+            L.qp_plan_query.argtypes = [_c_int32, _c_int32, _c_int32, ctypes.POINTER(_Opts),
+                                        ctypes.POINTER(_Plan)]
             L.qp_server_create.argtypes = [_vp, ctypes.POINTER(_ServerOpts), ctypes.POINTER(_Opts),
                                            ctypes.POINTER(_vp)]
             L.qp_serve_submit.argtypes = [_vp, _c_int32, _c_int32, _c_int32, _vp, _vp, _vp, _vp,
@@ -109,6 +117,19 @@ def lib() -> ctypes.CDLL:
 
 class QPError(RuntimeError):
     pass
+
+
+def plan(n: int, m: int, p: int, **kw) -> dict:
+    """Launch plan for one problem size (host only): threads per QP, border
+    cap, whether the factor fits LDS, assembly arithmetic, LDS bytes and
+    global workspace bytes per QP."""
+    o = make_opts(**kw)
+    pl = _Plan()
+    _check(lib().qp_plan_query(n, m, p, ctypes.byref(o), ctypes.byref(pl)), "qp_plan_query")
+    inv = {v: k for k, v in ASSEMBLY.items()}
+    return {"threads": pl.threads, "kb": pl.kb, "factor_in_lds": bool(pl.factor_in_lds),
+            "assembly": inv[pl.assembly], "lds_bytes": pl.lds_bytes,
+            "workspace_bytes": pl.workspace_bytes}
 
 
 def _check(rc: int, what: str):

@@ -153,6 +153,23 @@ int qp_destroy(qpx_ctx *ctx) {
   return QPX_OK;
 }
 
+int qp_plan_query(int32_t n, int32_t m, int32_t p, const qp_opts *opts, qp_plan *plan) {
+  if (!plan || n < 1 || m < 0 || p < 0 || p >= n) return QPX_ERR_ARG;
+  qp_opts o;
+  if (opts) o = *opts; else qp_default_opts(&o);
+  int rc = check_opts(o);
+  if (rc) return rc;
+  qpk::Plan pl;
+  if ((rc = qpk::make_plan(n, m, p, o, &pl))) return rc;
+  plan->threads = pl.threads;
+  plan->kb = pl.kb;
+  plan->factor_in_lds = pl.m_in_lds ? 1 : 0;
+  plan->assembly = pl.amode == 1 ? QPX_ASM_BF16X3 : (pl.amode == 2 ? QPX_ASM_MFMA_FP32 : QPX_ASM_FP32);
+  plan->lds_bytes = pl.lds;
+  plan->workspace_bytes = (size_t)pl.ws_stride * sizeof(float);
+  return QPX_OK;
+}
+
 int qp_solve(qpx_ctx *ctx, const qp_batch *bt, const qp_opts *opts, qp_out *out,
              void *stream) {
   if (!ctx || !out) return QPX_ERR_ARG;

@@ -56,7 +56,7 @@ def test_binding_structs_match_the_header():
     # the ctypes mirrors must list the header's fields in the header's order
     for cname, py in (("qp_batch", qpx._Batch), ("qp_opts", qpx._Opts), ("qp_out", qpx._Out),
                       ("qp_grads", qpx._Grads), ("qp_server_opts", qpx._ServerOpts),
-                      ("qp_timing", qpx._Timing)):
+                      ("qp_timing", qpx._Timing), ("qp_plan", qpx._Plan)):
         assert _struct_fields(cname) == [f[0] for f in py._fields_], cname
 
 
@@ -80,3 +80,35 @@ def test_cpu_tensors_raise():
     Q = torch.eye(3).unsqueeze(0)
     with pytest.raises(qpx.QPError):
         qpx.solve(Q, torch.zeros(1, 3), None, None, None, None)
+
+
+def test_launch_plans():
+    # host-side planning (no device call): border cap, threads per QP, factor
+    # placement, assembly arithmetic and size limits
+    c1 = qpx.plan(10, 20, 2)
+    assert c1["threads"] == 128 and c1["kb"] == 10 and c1["factor_in_lds"]
+    assert c1["assembly"] == "fp32" and c1["workspace_bytes"] == 0
+    c2 = qpx.plan(50, 100, 10)
+    assert c2["threads"] == 256 and c2["kb"] == 50 and c2["factor_in_lds"]
+    assert 3 * c2["lds_bytes"] <= 160 * 1024  # three QPs per CU
+    c3 = qpx.plan(100, 200, 20)
+    assert c3["kb"] == 100 and c3["factor_in_lds"] and c3["assembly"] == "mfma_fp32"
+    c5 = qpx.plan(256, 512, 32)
+    # factor in global memory: every row with v > 0 may be bordered
+    assert not c5["factor_in_lds"] and c5["kb"] == 512 and c5["threads"] == 512
+    assert c5["assembly"] == "mfma_fp32" and c5["workspace_bytes"] > 1 << 20
+    assert qpx.plan(256, 512, 32, kmax=256)["kb"] == 256
+    # the standard form and the first partially condensed form border nothing
+    assert qpx.plan(50, 100, 10, form="standard")["kb"] == 0
+    assert qpx.plan(256, 512, 32, form="condensed")["kb"] == 0
+    assert qpx.plan(256, 512, 32, form="standard")["assembly"] == "fp32"
+    assert qpx.plan(128, 256, 16, assembly="bf16x3")["assembly"] == "bf16x3"
+    # explicit block sizes: more than 512 rows need 512 threads
+    with pytest.raises(qpx.QPError):
+        qpx.plan(256, 512, 32, block=256)
+    with pytest.raises(qpx.QPError):
+        qpx.plan(1000, 10, 30)  # n + p beyond 1024 bordered rows
+    with pytest.raises(qpx.QPError):
+        qpx.plan(10, 5000, 1)   # m beyond 4096
+    with pytest.raises(qpx.QPError):
+        qpx.plan(10, 5, 10)     # p >= n
