@@ -24,7 +24,10 @@
  *    are detected on the host before anything is enqueued.  A per-QP
  *    numerical failure never fails the call: it is reported in status[].
  *  - Nothing here allocates per call except qp_solve / qp_backward's
- *    device workspace, which the context grows on demand and keeps.
+ *    device workspace, which the context grows on demand and keeps.  The
+ *    workspace is shared by the context's calls: a call on another stream
+ *    than the previous workspace user waits for that stream on the host.
+ *    Contexts are safe to use from several host threads.
  */
 #ifndef QPX_H
 #define QPX_H

@@ -19,9 +19,17 @@ int set_device(const qpx_ctx *ctx) {
   return hipSetDevice(ctx->device) == hipSuccess ? QPX_OK : QPX_ERR_HIP;
 }
 
-// Grow the workspace; the previous contents are not kept.  The caller's
-// stream is synchronised before freeing a buffer that may still be in use.
+// Make the workspace ready for a call on stream st: calls on another stream
+// than the previous user of the workspace wait for that stream first (the
+// workspace is shared by all calls of the context), and the buffer grows on
+// demand (previous contents are not kept; the device is synchronised before
+// a buffer that may still be in use is freed).
 int ensure_ws(qpx_ctx *ctx, size_t bytes, hipStream_t st) {
+  if (ctx->ws_used && ctx->ws_stream != st &&
+      hipStreamSynchronize(ctx->ws_stream) != hipSuccess)
+    return QPX_ERR_HIP;
+  ctx->ws_stream = st;
+  ctx->ws_used = true;
   if (bytes <= ctx->ws_bytes) return QPX_OK;
   if (ctx->ws) {
     if (hipDeviceSynchronize() != hipSuccess) return QPX_ERR_HIP;
@@ -29,7 +37,6 @@ int ensure_ws(qpx_ctx *ctx, size_t bytes, hipStream_t st) {
     ctx->ws = nullptr;
     ctx->ws_bytes = 0;
   }
-  (void)st;
   void *p = nullptr;
   if (hipMalloc(&p, bytes) != hipSuccess) return QPX_ERR_OOM;
   ctx->ws = static_cast<float *>(p);

@@ -151,6 +151,8 @@ struct qpx_ctx {
   int device = 0;
   float *ws = nullptr;     // global factor storage, grown on demand
   size_t ws_bytes = 0;
+  hipStream_t ws_stream = nullptr;  // stream of the last call that used ws
+  bool ws_used = false;
   std::mutex mu;           // guards ws growth
 };
 
