@@ -139,3 +139,25 @@ def test_ill_conditioned_gradients():
         err = np.linalg.norm(gg - ref[key]) / max(1e-3, np.linalg.norm(ref[key]))
         print(f"  d{key} err {err:.2e}", flush=True)
         assert err <= 1e-3, (key, err)
+
+
+def test_workspace_shared_across_streams():
+    # the context's global factor workspace is shared; solves enqueued on two
+    # streams one after the other must not overlap on it
+    import paper_2605_17913_amd as qpx
+    d = _dev()
+    P1 = qpgen.random_feasible(64, 128, 256, 16, seed=21)
+    P2 = qpgen.random_feasible(64, 128, 256, 16, seed=22)
+    T1 = [torch.from_numpy(a).to(d) for a in P1.arrays()]
+    T2 = [torch.from_numpy(a).to(d) for a in P2.arrays()]
+    ref1 = qpx.solve(*T1)["x"].cpu().numpy()
+    ref2 = qpx.solve(*T2)["x"].cpu().numpy()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    for _ in range(3):
+        with torch.cuda.stream(s1):
+            a = qpx.solve(*T1)
+        with torch.cuda.stream(s2):
+            b = qpx.solve(*T2)
+        torch.cuda.synchronize()
+        assert np.array_equal(a["x"].cpu().numpy(), ref1)
+        assert np.array_equal(b["x"].cpu().numpy(), ref2)
