@@ -438,8 +438,11 @@ QPD bool factor_panel(MF *M, int N, int npos, int k0, bool dyn, float &pmax, int
       const bool ok = tt > 0.f && tt <= FLT_MAX;
       if (ok) pmax = fmaxf(pmax, tt);
       fail |= !ok;
-      const float d = ok ? sqrtf(tt) : 1.f;
-      const float inv = sg / d;
+      // pivot sqrt(tt) and its signed inverse from one hardware reciprocal
+      // square root (about 1 ulp): this chain is on the panel's critical path
+      const float rs = ok ? __builtin_amdgcn_rsqf(tt) : 1.f;
+      const float d = ok ? tt * rs : 1.f;
+      const float inv = sg * rs;
       iv[jj] = inv;
       P0[jj] = lane > jj ? P0[jj] * inv : (lane == jj ? d : P0[jj]);
 #pragma unroll
