@@ -656,25 +656,6 @@ QPD void signed_solve_wave(const MF *M, int N, int npos, const lf *dinv, lf *r, 
   }
 }
 
-// FP64-accumulated y[i] = sum_j R[i*ld + j] x[j] (16 lanes per row).
-template <int T, class RF>
-QPD void rowdot_d(const RF *R, int ld, int rows, int cols, const lf *x, ldd *out) {
-  const int sub = threadIdx.x & 15, grp = threadIdx.x >> 4;
-#pragma unroll 2
-  for (int i0 = 0; i0 < rows; i0 += T / 16) {
-    const int i = i0 + grp;
-    double acc = 0.0;
-    if (i < rows) {
-      const RF *Ri = R + (size_t)i * ld;
-#pragma unroll 4
-      for (int j = sub; j < cols; j += 16) acc = fma((double)Ri[j], (double)x[j], acc);
-    }
-#pragma unroll
-    for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 16);
-    if (sub == 0 && i < rows) out[i] = acc;
-  }
-}
-
 // FP64-accumulated out[j] (+)= sum_i R[i*ld + j] x[i]; barriers inside.
 template <int T, class RF, class XF>
 QPD float coldot_d(const RF *R, int ld, int rows, int cols, const XF *x, ldd *out, bool add,
@@ -702,6 +683,91 @@ QPD float coldot_d(const RF *R, int ld, int rows, int cols, const XF *x, ldd *ou
     __syncthreads();
   }
   return mx;
+}
+
+// The products the residuals need, in one pass over Q, G and A (each n
+// columns wide), accumulated in FP64: gx = G x and ax = A x (row dots) and
+// rt = Q'x + G'z + A'y (column sums).  16 lanes share a row (columns
+// jb + sub + 16k, k < 4, in blocks of 64), T/16 rows at a time, with the
+// loads of several rows in flight before their arithmetic, so each input
+// element is read once.  The column sums of each matrix are reduced across
+// row groups (shuffles inside a wave, then `part`, T doubles, across
+// waves); their largest magnitudes, which scale the residuals, come back in
+// mq, mg, ma (per-thread partial maxima).  Without gcols, G contributes
+// its row dots only (z is not read).  No LDS pointer is tested against
+// NULL: LDS address 0 is a valid address.  Barriers inside.
+template <int T>
+QPD void kkt_matvecs(const gf *Q, const gf *G, const gf *A, int n, int m, int p, const lf *x,
+                     const lf *z, bool gcols, const lf *y, ldd *gx, ldd *ax, ldd *rt, ldd *part,
+                     float &mq, float &mg, float &ma) {
+  constexpr int RG = T / 16;
+  const int tid = threadIdx.x, sub = tid & 15, grp = tid >> 4, wid = tid >> 6;
+  mq = mg = ma = 0.f;
+  for (int jb = 0; jb < n; jb += 64) {
+    double xv[4], cq[4], cg[4], ca[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int j = jb + sub + 16 * k;
+      xv[k] = j < n ? (double)x[j] : 0.0;
+      cq[k] = cg[k] = ca[k] = 0.0;
+    }
+    // rows of R weighted by w (if cols) into c; with dots, also the row dots
+    // with x into out
+    auto sweep = [&](const gf *R, int rows, const lf *w, bool cols, ldd *out, bool dots,
+                     double(&c)[4]) {
+#pragma unroll 4
+      for (int i0 = 0; i0 < rows; i0 += RG) {
+        const int i = i0 + grp;
+        float e[4] = {0.f, 0.f, 0.f, 0.f};
+        double wi = 0.0;
+        if (i < rows) {
+          const gf *Ri = R + (size_t)i * n + jb + sub;
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+            if (jb + sub + 16 * k < n) e[k] = Ri[16 * k];
+          if (cols) wi = (double)w[i];
+        }
+        double d = 0.0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          c[k] = fma((double)e[k], wi, c[k]);
+          if (dots) d = fma((double)e[k], xv[k], d);
+        }
+        if (dots) {
+#pragma unroll
+          for (int o = 8; o > 0; o >>= 1) d += __shfl_xor(d, o, 16);
+          if (sub == 0 && i < rows) out[i] = jb ? out[i] + d : d;
+        }
+      }
+    };
+    sweep(Q, n, x, true, gx, false, cq);
+    if (m) sweep(G, m, z, gcols, gx, true, cg);
+    if (p) sweep(A, p, y, true, ax, true, ca);
+    // column sums across the row groups, one matrix at a time
+    auto reduce = [&](double(&c)[4], bool first, float &mx) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        c[k] += __shfl_xor(c[k], 16, 64);
+        c[k] += __shfl_xor(c[k], 32, 64);
+      }
+      if ((tid & 63) < 16) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) part[wid * 64 + 16 * k + sub] = c[k];
+      }
+      __syncthreads();
+      if (tid < 64 && jb + tid < n) {
+        double sum = 0.0;
+#pragma unroll
+        for (int w = 0; w < T / 64; ++w) sum += part[w * 64 + tid];
+        rt[jb + tid] = first ? sum : rt[jb + tid] + sum;
+        mx = fmaxf(mx, fabsf((float)sum));
+      }
+      __syncthreads();
+    };
+    reduce(cq, true, mq);
+    if (m && gcols) reduce(cg, false, mg);
+    if (p) reduce(ca, false, ma);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -799,15 +865,12 @@ QPK_PHASE float residuals(CT &Cin_, bool bounded, float kappa, float kr, bool *b
   // as they are produced
   ldd *gxd = C.dd, *axd = C.dd + m, *rtd = C.dd + m + p;
   ldd *pd = reinterpret_cast<ldd *>(C.part);
-  if (m) rowdot_d<T>(C.G, n, m, n, C.x, gxd);
-  if (p) rowdot_d<T>(C.A, n, p, n, C.x, axd);
   enum { RT, QX, QQ, GZ, AY, RI, GX, SS, HH, RE, AX, BB, RZS, ZZ, CC, NF, NK };
   float mx[NK];
 #pragma unroll
   for (int k = 0; k < NK; ++k) mx[k] = 0.f;
-  mx[QX] = coldot_d<T>(C.Q, n, n, n, C.x, rtd, false, pd);
-  if (m) mx[GZ] = coldot_d<T>(C.G, n, m, n, C.z, rtd, true, pd);
-  if (p) mx[AY] = coldot_d<T>(C.A, n, p, n, C.y, rtd, true, pd);
+  kkt_matvecs<T>(C.Q, C.G, C.A, n, m, p, C.x, C.z, true, C.y, gxd, axd, rtd, pd, mx[QX],
+                 mx[GZ], mx[AY]);
   for (int i = tid; i < n; i += T) {
     const float r = (float)(rtd[i] + (double)C.q[i]);
     C.rt[i] = r;
@@ -1269,18 +1332,17 @@ QPK_PHASE float refine(CT &Cin_, int nb, bool bounded, const lf *w, lf *u, int s
   lf *r = C.rr;
   float prev = 0.f, worst = 0.f;
   for (int it = 0; it < steps; ++it) {
-    if (m) rowdot_d<T>(C.G, n, m, n, u, gx);
-    if (p) rowdot_d<T>(C.A, n, p, n, u, ax);
-    __syncthreads();
+    // G u, A u and Q'u_x + A'u_y in one pass; then G' phi, which needs G u
+    float unused[3];
+    kkt_matvecs<T>(C.Q, C.G, C.A, n, m, p, u, u, false, u + n + nb, gx, ax, kx, pd, unused[0],
+                   unused[1], unused[2]);
     for (int i = tid; i < m; i += T) {
       const int k = C.role[i];
       const double wi = bounded ? (double)C.E[i] / (double)C.D[i] : (double)C.E[i];
       phi[i] = k >= 0 ? (double)u[n + k] : wi * gx[i];
     }
     __syncthreads();
-    coldot_d<T>(C.Q, n, n, n, u, kx, false, pd);
     if (m) coldot_d<T>(C.G, n, m, n, phi, kx, true, pd);
-    if (p) coldot_d<T>(C.A, n, p, n, u + n + nb, kx, true, pd);
     for (int j = tid; j < n; j += T) r[j] = (float)((double)w[j] - kx[j]);
     for (int k = tid; k < nb; k += T) {
       const int i = C.bidx[k];
@@ -1344,13 +1406,13 @@ QPK_PHASE void border_delta(CT &Cin_, int nb, float rel, float floor_abs) {
   __syncthreads();
 }
 
-// True (uniformly) if a[0..N) or b[0..N) (b may be null) holds a
+// True (uniformly) if a[0..N) or, with two, b[0..N) holds a
 // non-finite value.
 template <int T>
-QPD bool any_nonfinite(const lf *a, const lf *b, int N, lf *red) {
+QPD bool any_nonfinite(const lf *a, const lf *b, bool two, int N, lf *red) {
   float f[1] = {0.f};
   for (int j = threadIdx.x; j < N; j += T) {
-    if (!finitef(a[j]) || (b && !finitef(b[j]))) f[0] = 1.f;
+    if (!finitef(a[j]) || (two && !finitef(b[j]))) f[0] = 1.f;
   }
   block_reduce<T, OpMax, 1>(f, red);
   return f[0] != 0.f;
@@ -1613,7 +1675,7 @@ QPK_PHASE int newton_bounded(CT &Cin_, float &kappa, int kt_mode, float sigma, f
     }
     // a factor that passed its checks can still give a non-finite solution
     // when it is nearly singular: redo the step once with a border floor
-    if (C.dyn && !floor && any_nonfinite<T>(C.u0, C.u1, N, C.red)) {
+    if (C.dyn && !floor && any_nonfinite<T>(C.u0, C.u1, true, N, C.red)) {
       floor = true;
       continue;
     }
@@ -1919,7 +1981,7 @@ QPK_PHASE bool adjoint(CT &Cin_, bool bounded, const gf *gx, const gf *gy, const
         __syncthreads();
         continue;
       }
-      if (C.dyn && !floor && any_nonfinite<T>(C.u0, nullptr, N, C.red)) {
+      if (C.dyn && !floor && any_nonfinite<T>(C.u0, C.u0, false, N, C.red)) {
         floor = true;
         continue;
       }
