@@ -254,70 +254,106 @@ __host__ __device__ inline Layout make_layout(int n, int m, int p, int kb, bool 
 // ---------------------------------------------------------------------------
 // Dense helpers on one workgroup of T threads.
 
-// out[i] = sum_j R[i*ld + j] x[j] for i < rows (16 lanes per row).
+// out[i] = sum_j R[i*ld + j] x[j] for i < rows.  16 lanes share a row
+// (columns jb + sub + 16c, c < 4, in blocks of 64) and T/16 rows go at a
+// time; the row loop is unrolled so that the loads of several rows are in
+// flight before their arithmetic.
 template <int T, int NV, class RF>
 QPD void rowdot(const RF *R, int ld, int rows, int cols, const lf *const (&x)[NV],
                 lf *const (&out)[NV]) {
   const int sub = threadIdx.x & 15, grp = threadIdx.x >> 4;
-#pragma unroll 2
-  for (int i0 = 0; i0 < rows; i0 += T / 16) {
-    const int i = i0 + grp;
-    float acc[NV];
+  for (int jb = 0; jb < cols; jb += 64) {
+    float xv[NV][4];
 #pragma unroll
-    for (int k = 0; k < NV; ++k) acc[k] = 0.f;
-    if (i < rows) {
-      const RF *Ri = R + (size_t)i * ld;
+    for (int c = 0; c < 4; ++c) {
+      const int j = jb + sub + 16 * c;
+#pragma unroll
+      for (int k = 0; k < NV; ++k) xv[k][c] = j < cols ? x[k][j] : 0.f;
+    }
 #pragma unroll 4
-      for (int j = sub; j < cols; j += 16) {
-        const float r = Ri[j];
+    for (int i0 = 0; i0 < rows; i0 += T / 16) {
+      const int i = i0 + grp;
+      float e[4] = {0.f, 0.f, 0.f, 0.f};
+      if (i < rows) {
+        const RF *Ri = R + (size_t)i * ld + jb + sub;
 #pragma unroll
-        for (int k = 0; k < NV; ++k) acc[k] = fmaf(r, x[k][j], acc[k]);
+        for (int c = 0; c < 4; ++c)
+          if (jb + sub + 16 * c < cols) e[c] = Ri[16 * c];
       }
-    }
+      float acc[NV];
 #pragma unroll
-    for (int k = 0; k < NV; ++k) {
+      for (int k = 0; k < NV; ++k) {
+        acc[k] = 0.f;
 #pragma unroll
-      for (int o = 8; o > 0; o >>= 1) acc[k] += __shfl_xor(acc[k], o, 16);
-    }
-    if (sub == 0 && i < rows) {
+        for (int c = 0; c < 4; ++c) acc[k] = fmaf(e[c], xv[k][c], acc[k]);
 #pragma unroll
-      for (int k = 0; k < NV; ++k) out[k][i] = acc[k];
+        for (int o = 8; o > 0; o >>= 1) acc[k] += __shfl_xor(acc[k], o, 16);
+      }
+      if (sub == 0 && i < rows) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) out[k][i] = jb ? out[k][i] + acc[k] : acc[k];
+      }
     }
   }
 }
 
-// out[j] = sum_i R[i*ld + j] x[i] for j < cols.  Threads split the rows in
-// groups and combine partial sums through `part` (T floats).  Contains
-// barriers; `x` must be visible to all threads on entry.
+// out[j] = sum_i R[i*ld + j] x[i] for j < cols.  The same lane layout as
+// rowdot (16 lanes per row, 4 columns each, T/16 rows at a time, several
+// rows' loads in flight); each lane sums its columns over its rows, then the
+// row groups are combined by shuffles inside a wave and through `part`
+// (2T floats) across waves.  Barriers inside; `x` must be visible to all
+// threads on entry.
 template <int T, int NV, class RF>
 QPD void coldot(const RF *R, int ld, int rows, int cols, const lf *const (&x)[NV],
                 lf *const (&out)[NV], lf *part) {
   static_assert(NV <= 2, "part holds two floats per thread");
-  const int cw = cols <= 64 ? 64 : (cols <= 128 ? (T >= 128 ? 128 : 64) : (T >= 256 ? 256 : T));
-  const int groups = T / cw;
-  const int g = threadIdx.x / cw, jl = threadIdx.x % cw;
-  for (int jb = 0; jb < cols; jb += cw) {
-    const int j = jb + jl;
-    float acc[NV];
+  const int tid = threadIdx.x, sub = tid & 15, grp = tid >> 4, wid = tid >> 6;
+  for (int jb = 0; jb < cols; jb += 64) {
+    float c[NV][4];
 #pragma unroll
-    for (int k = 0; k < NV; ++k) acc[k] = 0.f;
-    if (j < cols) {
-#pragma unroll 8
-      for (int i = g; i < rows; i += groups) {
-        const float r = R[(size_t)i * ld + j];
+    for (int k = 0; k < NV; ++k)
 #pragma unroll
-        for (int k = 0; k < NV; ++k) acc[k] = fmaf(r, x[k][i], acc[k]);
+      for (int q = 0; q < 4; ++q) c[k][q] = 0.f;
+#pragma unroll 4
+    for (int i0 = 0; i0 < rows; i0 += T / 16) {
+      const int i = i0 + grp;
+      float e[4] = {0.f, 0.f, 0.f, 0.f}, w[NV];
+#pragma unroll
+      for (int k = 0; k < NV; ++k) w[k] = 0.f;
+      if (i < rows) {
+        const RF *Ri = R + (size_t)i * ld + jb + sub;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (jb + sub + 16 * q < cols) e[q] = Ri[16 * q];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) w[k] = x[k][i];
       }
+#pragma unroll
+      for (int k = 0; k < NV; ++k)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) c[k][q] = fmaf(e[q], w[k], c[k][q]);
     }
 #pragma unroll
-    for (int k = 0; k < NV; ++k) part[k * T + threadIdx.x] = acc[k];
+    for (int k = 0; k < NV; ++k)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        c[k][q] += __shfl_xor(c[k][q], 16, 64);
+        c[k][q] += __shfl_xor(c[k][q], 32, 64);
+      }
+    if ((tid & 63) < 16) {
+#pragma unroll
+      for (int k = 0; k < NV; ++k)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) part[k * T + wid * 64 + 16 * q + sub] = c[k][q];
+    }
     __syncthreads();
-    if (g == 0 && j < cols) {
+    if (tid < 64 && jb + tid < cols) {
 #pragma unroll
       for (int k = 0; k < NV; ++k) {
-        float s = 0.f;
-        for (int gg = 0; gg < groups; ++gg) s += part[k * T + gg * cw + jl];
-        out[k][j] = s;
+        float sum = 0.f;
+#pragma unroll
+        for (int w = 0; w < T / 64; ++w) sum += part[k * T + w * 64 + tid];
+        out[k][jb + tid] = sum;
       }
     }
     __syncthreads();
@@ -1257,29 +1293,28 @@ QPK_PHASE void assemble(CT &Cin_, int nb, int ne, const lf *wts, bool bounded, f
   }
   }
   __syncthreads();
-  // border rows: [C | -Dl (lower part)]
+  // border rows: [C | -Dl (lower part)].  C = [G_B; A] as row copies with
+  // several loads in flight, then the lower triangle of the diagonal block.
   const int K = nb + p;
-  for (int e = tid; e < K * (n + K); e += T) {
-    const int k = e / (n + K), col = e % (n + K);
-    const int row = n + k;
-    if (col > row) continue;
-    float val;
-    if (col < n) {
-      val = k < nb ? C.G[(size_t)C.bidx[k] * n + col] : C.A[(size_t)(k - nb) * n + col];
-    } else {
-      const int l = col - n;
-      if (l != k) {
-        val = 0.f;
-      } else {
-        float dl = 0.f;
-        if (k < nb && bounded) {
-          const int r = C.bidx[k];
-          dl = C.D[r] / C.E[r];
-        }
-        val = -(dl + delta);
+#pragma unroll 4
+  for (int e = tid; e < K * n; e += T) {
+    const int k = e / n, col = e - k * n;
+    M[moff(n + k) + col] =
+        k < nb ? C.G[(size_t)C.bidx[k] * n + col] : C.A[(size_t)(k - nb) * n + col];
+  }
+  for (int e = tid; e < K * K; e += T) {
+    const int k = e / K, l = e - k * K;
+    if (l > k) continue;
+    float val = 0.f;
+    if (l == k) {
+      float dl = 0.f;
+      if (k < nb && bounded) {
+        const int r = C.bidx[k];
+        dl = C.D[r] / C.E[r];
       }
+      val = -(dl + delta);
     }
-    M[moff(row) + col] = val;
+    M[moff(n + k) + n + l] = val;
   }
   __syncthreads();
 }
