@@ -254,6 +254,23 @@ __host__ __device__ inline Layout make_layout(int n, int m, int p, int kb, bool 
 // ---------------------------------------------------------------------------
 // Dense helpers on one workgroup of T threads.
 
+// Columns jb + sub + 16q (q < 4) of row i of R (rows x cols, row stride
+// ld), loaded from clamped in-bounds addresses without a branch, so that
+// the loads of an unrolled row loop issue together; entries outside the
+// matrix read as 0.  Needs rows >= 1 and cols >= 1.
+template <class RF>
+QPD void load_row4(const RF *R, int ld, int rows, int cols, int i, int jb, int sub,
+                   float (&e)[4]) {
+  const bool in = i < rows;
+  const RF *Ri = R + (size_t)(in ? i : rows - 1) * ld;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int j = jb + sub + 16 * q;
+    const float v = Ri[min(j, cols - 1)];
+    e[q] = (in && j < cols) ? v : 0.f;
+  }
+}
+
 // out[i] = sum_j R[i*ld + j] x[j] for i < rows.  16 lanes share a row
 // (columns jb + sub + 16c, c < 4, in blocks of 64) and T/16 rows go at a
 // time; the row loop is unrolled so that the loads of several rows are in
@@ -1250,10 +1267,28 @@ QPK_PHASE void assemble(CT &Cin_, int nb, int ne, const lf *wts, bool bounded, f
     for (int k0 = 0; k0 < ne; k0 += R) {
       const int kr = min(R, ne - k0);
       __syncthreads();  // the previous chunk has been consumed
-#pragma unroll 4
-      for (int e = tid; e < kr * ldg; e += T) {
-        const int r = e / ldg, j = e - r * ldg;
-        stage[e] = j < n ? C.G[(size_t)C.elist[k0 + r] * n + j] : 0.f;
+      // 16 lanes per staged row (4 columns each, blocks of 64), T/16 rows at
+      // a time: the loads of four row batches first, then the stores
+      for (int jb = 0; jb < ldg; jb += 64) {
+        for (int r0 = 0; r0 < kr; r0 += 4 * (T / 16)) {
+          float e[4][4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int r = min(r0 + u * (T / 16) + (tid >> 4), kr - 1);
+            load_row4(C.G + (size_t)C.elist[k0 + r] * n, n, 1, n, 0, jb, tid & 15, e[u]);
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int r = r0 + u * (T / 16) + (tid >> 4);
+            if (r < kr) {
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                const int j = jb + (tid & 15) + 16 * q;
+                if (j < ldg) stage[r * ldg + j] = e[u][q];
+              }
+            }
+          }
+        }
       }
       __syncthreads();
       if (act) {
