@@ -2307,22 +2307,27 @@ QPD void qp_body(const Params &P) {
 #endif
 }
 
+// Waves per SIMD the register allocation targets: 3 (168 VGPRs) up to 256
+// threads per QP, 2 (256 VGPRs) at 512.  At 128 threads, 4 waves (128 VGPRs)
+// spilled about twice as much and ran 24% slower on n = 10 and n = 20.
+#define QPK_MIN_WAVES(T) ((T) >= 512 ? 2 : 3)
+
 // One workgroup per QP: Algorithm 1 (or the standard IPM) end to end.
 template <int T, int RPL, bool MLDS>
-__global__ void __launch_bounds__(T, (T >= 512 ? 2 : (T >= 256 ? 3 : 4))) qp_solve_kernel(Params P) {
+__global__ void __launch_bounds__(T, QPK_MIN_WAVES(T)) qp_solve_kernel(Params P) {
   qp_body<T, RPL, MLDS, kSolve>(P);
 }
 
 // One workgroup per QP: relax (Algorithm 2), adjoint solve and parameter
 // gradients (Algorithm 3).
 template <int T, int RPL, bool MLDS>
-__global__ void __launch_bounds__(T, (T >= 512 ? 2 : (T >= 256 ? 3 : 4))) qp_backward_kernel(Params P) {
+__global__ void __launch_bounds__(T, QPK_MIN_WAVES(T)) qp_backward_kernel(Params P) {
   qp_body<T, RPL, MLDS, kBackward>(P);
 }
 
 // One workgroup per resident serving slot: resume its Newton loop.
 template <int T, int RPL, bool MLDS>
-__global__ void __launch_bounds__(T, (T >= 512 ? 2 : (T >= 256 ? 3 : 4))) qp_serve_kernel(Params P) {
+__global__ void __launch_bounds__(T, QPK_MIN_WAVES(T)) qp_serve_kernel(Params P) {
   qp_body<T, RPL, MLDS, kServe>(P);
 }
 
