@@ -107,17 +107,31 @@ inline int make_plan(int n, int m, int p, const qp_opts &o, Plan *pl) {
   pl->threads = T;
   const size_t lim = qpk::lds_limit();
   const size_t with_m = qpk::lds_bytes(n, m, p, kb, true, T);
-  if (with_m <= lim) {
+  // QPs resident per CU: LDS-limited, and at most the waves the register
+  // allocation targets (three per SIMD up to 256 threads, two at 512).  A
+  // factor that fits LDS but halves (or worse) the residency of the
+  // global-factor layout goes to global memory instead: at n = 100 the LDS
+  // factor leaves one QP per CU, the global one three (15% faster).
+  const size_t cu_lds = lim;
+  const int cu_waves = 4 * (T >= 512 ? 2 : 3);
+  auto per_cu = [&](size_t bytes) {
+    return std::min<size_t>(cu_lds / std::max<size_t>(bytes, 1), cu_waves / (T / 64));
+  };
+  const bool fits = with_m <= lim;
+  const bool prefer_global =
+      fits && per_cu(qpk::lds_bytes(n, m, p, kb, false, T)) >= 2 * per_cu(with_m);
+  if (fits && !prefer_global) {
     pl->m_in_lds = true;
     pl->lds = with_m;
     pl->ws_stride = 0;
   } else {
     pl->m_in_lds = false;
-    // The factor lives in global memory anyway: with the automatic cap,
-    // border every row with v > 0 (up to m, within kMaxN), which keeps every
+    // When the factor cannot fit LDS at all, the automatic cap borders
+    // every row with v > 0 (up to m, within kMaxN), which keeps every
     // multiplier bounded also when more than n rows are active.  This costs
-    // workspace, not LDS occupancy.
-    if (o.kmax == 0 && o.form == QPX_BOUNDED) {
+    // workspace, not LDS occupancy.  (A factor moved out of LDS only for
+    // residency keeps the border of the LDS layout: same system.)
+    if (!fits && o.kmax == 0 && o.form == QPX_BOUNDED) {
       const int kb2 = std::min(m, kMaxN - n - p);
       const int N2 = n + kb2 + p;
       const int T2 = o.block ? o.block : (N2 <= 256 ? 256 : 512);
@@ -133,11 +147,11 @@ inline int make_plan(int n, int m, int p, const qp_opts &o, Plan *pl) {
     if (pl->lds > lim) return QPX_ERR_UNSUPPORTED;
     pl->ws_stride = qpk::ws_floats(n, m, p, kb);
   }
-  const bool fits = qpk::mfma_stage_fits(n, m, p, kb, pl->m_in_lds, T);
+  const bool stage_fits = qpk::mfma_stage_fits(n, m, p, kb, pl->m_in_lds, T);
   int am = o.assembly;
   if (am == QPX_ASM_AUTO)
-    am = (o.form == QPX_BOUNDED && n >= 96 && fits) ? QPX_ASM_MFMA_FP32 : QPX_ASM_FP32;
-  else if (am != QPX_ASM_FP32 && !fits)
+    am = (o.form == QPX_BOUNDED && n >= 96 && stage_fits) ? QPX_ASM_MFMA_FP32 : QPX_ASM_FP32;
+  else if (am != QPX_ASM_FP32 && !stage_fits)
     return QPX_ERR_UNSUPPORTED;
   pl->amode = am == QPX_ASM_BF16X3 ? 1 : (am == QPX_ASM_MFMA_FP32 ? 2 : 0);
   return QPX_OK;

@@ -92,7 +92,11 @@ def test_launch_plans():
     assert c2["threads"] == 256 and c2["kb"] == 50 and c2["factor_in_lds"]
     assert 3 * c2["lds_bytes"] <= 160 * 1024  # three QPs per CU
     c3 = qpx.plan(100, 200, 20)
-    assert c3["kb"] == 100 and c3["factor_in_lds"] and c3["assembly"] == "mfma_fp32"
+    # the factor would fit LDS (131 KB) but leave one QP per CU; in global
+    # memory three fit (register-limited), with the same border
+    assert c3["kb"] == 100 and not c3["factor_in_lds"] and c3["assembly"] == "mfma_fp32"
+    assert c3["threads"] == 256 and c3["lds_bytes"] * 3 <= 160 * 1024
+    assert c3["workspace_bytes"] > 0
     c5 = qpx.plan(256, 512, 32)
     # factor in global memory: every row with v > 0 may be bordered
     assert not c5["factor_in_lds"] and c5["kb"] == 512 and c5["threads"] == 512
