@@ -97,6 +97,16 @@ def test_launch_plans():
     assert c3["kb"] == 100 and not c3["factor_in_lds"] and c3["assembly"] == "mfma_fp32"
     assert c3["threads"] == 256 and c3["lds_bytes"] * 3 <= 160 * 1024
     assert c3["workspace_bytes"] > 0
+    # residency rule: the factor leaves LDS only when that at least doubles
+    # the QPs per CU (capped at 12 waves per CU below 512 threads)
+    small = qpx.plan(30, 60, 3)
+    assert small["threads"] == 128 and small["factor_in_lds"]
+    mid = qpx.plan(80, 160, 8)
+    assert mid["threads"] == 256 and not mid["factor_in_lds"] and mid["kb"] == 80
+    assert mid["lds_bytes"] * 3 <= 160 * 1024
+    narrow = qpx.plan(50, 100, 10, block=128)
+    assert not narrow["factor_in_lds"] and narrow["kb"] == 50
+    assert narrow["lds_bytes"] * 6 <= 160 * 1024
     c5 = qpx.plan(256, 512, 32)
     # factor in global memory: every row with v > 0 may be bordered
     assert not c5["factor_in_lds"] and c5["kb"] == 512 and c5["threads"] == 512
