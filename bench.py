@@ -10,9 +10,11 @@ to kappa_relax = 1e-4 (Algorithm 2), adjoint solve and parameter gradients
 
 Printed: one JSON line.  value = fwd+bwd QPs per second of the timed steps;
 extra fields give forward-only solves/s, the roofline of the dominant kernel
-(the fused solve kernel), the FP64 oracle timed on the host cores, the
-standard-form ablation on the same inputs, the serving loop's throughput and
-p50/p99 latency, and the rates of the differentiation (n=100) and
+(the fused solve kernel) and of every other hot kernel (`kernels`), the same
+step under the FP64-residual policy (`precision`), the oracle timed on the
+host cores in FP64 and in FP32 (the plain per-QP path), the standard-form
+ablation on the same inputs, the serving loop's throughput and p50/p99
+latency per size class, and the rates of the differentiation (n=100) and
 ill-conditioned (n=256) configurations.
 
 --calibrate-copy runs only a device-to-device copy of a known size; its
@@ -35,51 +37,115 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "QP solves/s + fwd+bwd/s at 1e-5 KKT residual (FP32 vs plain); p50/p99 latency"
-KERNEL_SRC = os.path.join(ROOT, "paper_2605_17913_amd", "csrc", "qp_kernel_impl.hpp")
+CSRC = os.path.join(ROOT, "paper_2605_17913_amd", "csrc")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_qp_solve_kernel_n50_m100_p10.json")
 
 PEAK_ALU = 78.6      # TFLOP/s: 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz (FP32 FMA, unpacked)
 PEAK_ALU_PACKED = 157.3
+PEAK_MFMA_FP32 = 157.3  # TFLOP/s, dense FP32 matrix cores
 PEAK_HBM = 8000.0    # GB/s
 
+# The ill-conditioned workload is solved to 1e-6 (at 1e-5 its scaled residual
+# does not bound the error in x to 1e-4) and differentiated at
+# kappa_relax = 1e-3 (float32 cannot resolve its relaxed system at 1e-4).
+ILL_TOL = 1e-6
+ILL_KAPPA_RELAX = 1e-3
 
-def _oracle_worker(work):
-    """One step of the workload per QP with the FP64 oracle: solve to 1e-5,
-    relax to kappa_relax = 1e-4 from that point, IFT vector-Jacobian product."""
+
+def _oracle_worker(args):
+    """One step of the workload per QP with the oracle: solve to 1e-5, relax
+    to kappa_relax = 1e-4 from that point, IFT vector-Jacobian product.
+    dtype float64 is the oracle as it stands; float32 runs the same code in
+    single precision (the plain per-QP FP32 path; the IFT product itself is
+    float64 in the oracle).  Returns (busy seconds, QPs, converged)."""
+    work, dtype = args
     import threadpoolctl
     from oracle import gradients, implicit
-    with threadpoolctl.threadpool_limits(1):
+    with threadpoolctl.threadpool_limits(1), np.errstate(all="ignore"):
         t0 = time.perf_counter()
+        conv = 0
         for prob, gx in work:
-            r = implicit.solve_qp(*prob, tol=1e-5)
-            gradients.grad_at_relaxed(*prob, 1e-4, gx, warm=(r.x, r.y, r.z, r.s))
-        return time.perf_counter() - t0, len(work)
+            r = implicit.solve_qp(*prob, tol=1e-5, dtype=dtype)
+            rr = implicit.relax_qp(*prob, r.x, r.y, r.z, r.s, 1e-4, tol=1e-6, dtype=dtype)
+            if dtype == np.float64:
+                gradients.ift_vjp(*prob, rr.x, rr.y, rr.z, rr.s, gx)
+            elif np.all(np.isfinite(rr.x)):
+                gradients.ift_vjp(*prob, rr.x, rr.y, rr.z, rr.s, gx)
+            conv += int(r.status == 0 and rr.status == 0)
+        return time.perf_counter() - t0, len(work), conv
 
 
-def cpu_baseline(P, gx, budget_s=15.0):
-    """The FP64 oracle (Algorithm 1 with dense LU on the uncondensed system,
-    Algorithm 2, the IFT product from the transposed standard Jacobian) on a
-    bounded sample of the same workload, one QP per worker process."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_rate(P, gx, dtype, workers, budget_s):
+    """QPs/s of the oracle step on `workers` processes (1 BLAS thread each),
+    on the first QPs of the batch, sized to about budget_s seconds of work
+    per worker."""
     import multiprocessing as mp
-    cores = min(16, os.cpu_count() or 1)
-    t, _ = _oracle_worker([(P.one(0), gx[0])])  # calibrate
-    n_qp = int(min(P.B, max(cores, budget_s * cores / max(t, 1e-4))))
-    chunks = [[(P.one(i), gx[i]) for i in range(c, n_qp, cores)] for c in range(cores)]
-    t0 = time.perf_counter()
-    with mp.get_context("spawn").Pool(cores) as pool:
-        res = pool.map(_oracle_worker, [c for c in chunks if c])
-    wall = time.perf_counter() - t0
+    t, _, _ = _oracle_worker(([(P.one(0), gx[0])], dtype))  # calibrate
+    n_qp = int(min(P.B, max(workers, budget_s * workers / max(t, 1e-4))))
+    chunks = [[(P.one(i), gx[i]) for i in range(c, n_qp, workers)] for c in range(workers)]
+    if workers == 1:
+        res = [_oracle_worker((chunks[0], dtype))]
+    else:
+        with mp.get_context("spawn").Pool(workers) as pool:
+            res = pool.map(_oracle_worker, [(c, dtype) for c in chunks if c])
     done = sum(r[1] for r in res)
     busy = max(r[0] for r in res)
-    return {"value": round(done / busy, 2), "unit": "QPs/s", "cores": cores, "kind": "oracle",
-            "sample": f"first {done} of the {P.B} QPs, FP64 oracle solve to tol 1e-5 + relax to "
-                      f"kappa 1e-4 + IFT gradient, {cores} worker processes with 1 BLAS thread "
-                      f"each ({wall:.1f} s wall)"}
+    return {"value": round(done / busy, 2), "qps": done, "converged": sum(r[2] for r in res)}
+
+
+def cpu_baseline(P, gx, budget_s=6.0):
+    """The oracle on a bounded sample of the same workload: FP64 (the oracle
+    as it stands) and FP32 (the plain per-QP path), each on one core and on
+    every core of this process's CPU set, one QP per worker process."""
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    cores = max(1, min(16, cores))
+    all64 = _oracle_rate(P, gx, np.float64, cores, budget_s)
+    one64 = _oracle_rate(P, gx, np.float64, 1, budget_s)
+    all32 = _oracle_rate(P, gx, np.float32, cores, budget_s)
+    one32 = _oracle_rate(P, gx, np.float32, 1, budget_s)
+    return {"value": all64["value"], "unit": "QPs/s", "cores": cores, "kind": "oracle",
+            "sample": f"first {all64['qps']} of the {P.B} QPs (all cores) and {one64['qps']} "
+                      f"(one core): oracle solve to tol 1e-5 + relax to kappa 1e-4 + IFT "
+                      f"gradient, one QP per worker process with 1 BLAS thread",
+            "one_core": one64["value"],
+            "plain_fp32": {"all_cores": all32["value"], "one_core": one32["value"],
+                           "converged_frac": round(all32["converged"] / max(1, all32["qps"]), 3),
+                           "note": "the same oracle code in float32 (IFT product in float64)"},
+            "nproc": os.cpu_count(), "cpu_set": cores, "cpu_model": _cpu_model()}
 
 
 def kernel_source_hash():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of every source the kernels are built from (csrc/ and the
+    C-ABI header): a change to any of them invalidates stored counters."""
+    h = hashlib.sha256()
+    files = sorted(f for f in os.listdir(CSRC) if f.endswith((".hpp", ".hip", ".cpp", ".h")))
+    for name in files + ["../../include/qpx.h"]:
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def kernel_name(kind, n, m, p, **kw):
+    """Name of the fused kernel the library launches for one problem size
+    (from its launch plan)."""
+    import paper_2605_17913_amd as qpx
+    pl = qpx.plan(n, m, p, **kw)
+    rpl = (n + pl["kb"] + p + 63) // 64
+    rpl = 1 if rpl <= 1 else 2 if rpl <= 2 else 4 if rpl <= 4 else 8 if rpl <= 8 else 16
+    lds = "true" if pl["factor_in_lds"] else "false"
+    return f"qp_{kind}_kernel<{pl['threads']}, {rpl}, {lds}>"
 
 
 def measured_traffic(launch_s):
@@ -94,7 +160,18 @@ def measured_traffic(launch_s):
         return None
     byts = t["bytes_per_launch"]
     return {"bytes_per_launch": byts, "GB_per_s": round(byts / launch_s / 1e9, 1),
-            "hbm_frac": round(byts / launch_s / 1e9 / PEAK_HBM, 4), "source": os.path.basename(TRAFFIC_FILE)}
+            "hbm_frac": round(byts / launch_s / 1e9 / PEAK_HBM, 4),
+            "source": os.path.basename(TRAFFIC_FILE)}
+
+
+def grad_bytes(B, n, m, p):
+    """Bytes of the parameter gradients one backward launch writes (a14)."""
+    return 4 * B * (n * n + n + p * n + p + m * n + m)
+
+
+def roofline_entry(kernel, bound, achieved, peak, unit, launch_ms, **extra):
+    return dict(kernel=kernel, bound=bound, achieved=round(achieved, 3), peak=peak, unit=unit,
+                frac=round(achieved / peak, 4), launch_ms=round(launch_ms, 3), **extra)
 
 
 def calibrate_copy(mib=512, reps=5):
@@ -109,30 +186,45 @@ def calibrate_copy(mib=512, reps=5):
     return {"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "reps": reps}
 
 
-def config_rate(qpx, torch, P, steps=3, backward=True, **kw):
-    """Solves/s (and fwd+bwd/s) of one extra configuration, inputs resident."""
+def timed_config(qpx, torch, P, steps=3, backward=True, kappa_relax=1e-4, **kw):
+    """Solves/s (and fwd+bwd/s) of one configuration with inputs resident,
+    each launch timed with HIP events on its stream, plus the kernels'
+    algorithmic flops (the `work` counters)."""
+    import qpgen
     dev = torch.device("cuda:0")
     Q, q, A, b, G, h = (torch.from_numpy(a).to(dev) for a in P.arrays())
-    import qpgen
     gx = torch.from_numpy(qpgen.upstream(P.B, P.Q.shape[1], 11)).to(dev)
-    opts = qpx.make_opts(tol=1e-5, kappa_relax=1e-4, **kw)
+    opts = qpx.make_opts(kappa_relax=kappa_relax, **kw)
     sol = qpx.solve(Q, q, A, b, G, h, opts=opts)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        sol = qpx.solve(Q, q, A, b, G, h, opts=opts)
-    torch.cuda.synchronize()
-    t_fwd = (time.perf_counter() - t0) / steps
-    out = {"solves_per_s": round(P.B / t_fwd, 1),
-           "converged_frac": float(np.mean((sol["status"].cpu().numpy() & 0xFF) == 0)),
-           "iters_mean": float(sol["iters"].float().mean().item())}
     if backward:
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            s2 = qpx.solve(Q, q, A, b, G, h, opts=opts)
-            qpx.backward(Q, q, A, b, G, h, s2, gx, opts=opts)
+        qpx.backward(Q, q, A, b, G, h, sol, gx, opts=opts)
+    torch.cuda.synchronize()
+    fwd, bwd = [], []
+    for _ in range(steps):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record()
+        sol = qpx.solve(Q, q, A, b, G, h, opts=opts, work=True)
+        e[1].record()
+        if backward:
+            g = qpx.backward(Q, q, A, b, G, h, sol, gx, opts=opts, work=True)
+        e[2].record()
         torch.cuda.synchronize()
-        out["fwd_bwd_per_s"] = round(P.B / ((time.perf_counter() - t0) / steps), 1)
+        fwd.append(e[0].elapsed_time(e[1]) * 1e-3)
+        bwd.append(e[1].elapsed_time(e[2]) * 1e-3)
+    st = sol["status"].cpu().numpy()
+    tf, tb = float(np.median(fwd)), float(np.median(bwd))
+    out = {"solves_per_s": round(P.B / tf, 1),
+           "converged_frac": float(np.mean((st & 0xFF) == 0)),
+           "fp64_refinement_frac": float(np.mean((st >> 16) & 1)),
+           "iters_mean": float(sol["iters"].float().mean().item()),
+           "fwd_ms": round(tf * 1e3, 3), "fwd_flops": float(sol["work"].sum().item())}
+    if kw.get("assembly") == "bf16x3":
+        out["bf16x3_fallback_frac"] = float(np.mean((st >> 17) & 1))
+    if backward:
+        rst = g["relaxed"]["status"].cpu().numpy()
+        out.update({"fwd_bwd_per_s": round(P.B / (tf + tb), 1), "bwd_ms": round(tb * 1e3, 3),
+                    "relax_converged_frac": float(np.mean((rst & 0xFF) == 0)),
+                    "bwd_flops": float(g["relaxed"]["work"].sum().item())})
     return out
 
 
@@ -175,19 +267,26 @@ def serving_bench(n_requests=1200, seed=7, rates=(0.5, 0.9), max_slots=512, iter
             while k < n_requests or pending:
                 now = time.perf_counter() - t0
                 while k < n_requests and arr[k] <= now:
-                    pending[srv.submit(*probs[k])] = None
+                    pending[srv.submit(*probs[k])] = sizes[k][0]
                     k += 1
                 for t in list(pending):
                     r = srv.poll(t)
                     if r is not None:
-                        lat.append(r["t_done"] - r["t_submit"])
+                        lat.append((r["t_done"] - r["t_submit"], pending[t]))
                         del pending[t]
                 if k < n_requests and not pending:
                     time.sleep(max(0.0, min(1e-3, arr[k] - (time.perf_counter() - t0))))
-            lat = np.array(lat) * 1e3
-            out[f"rate_{frac:.2f}"] = {"offered_per_s": round(lam, 1),
-                                       "p50_ms": round(float(np.percentile(lat, 50)), 3),
-                                       "p99_ms": round(float(np.percentile(lat, 99)), 3)}
+            lat = np.array([l for l, _ in lat]) * 1e3, np.array([n for _, n in lat])
+            row = {"offered_per_s": round(lam, 1),
+                   "p50_ms": round(float(np.percentile(lat[0], 50)), 3),
+                   "p99_ms": round(float(np.percentile(lat[0], 99)), 3), "by_n": {}}
+            for lo, hi in ((8, 64), (65, 128), (129, 256)):
+                sel = lat[0][(lat[1] >= lo) & (lat[1] <= hi)]
+                if sel.size:
+                    row["by_n"][f"{lo}-{hi}"] = {
+                        "count": int(sel.size), "p50_ms": round(float(np.percentile(sel, 50)), 3),
+                        "p99_ms": round(float(np.percentile(sel, 99)), 3)}
+            out[f"rate_{frac:.2f}"] = row
     return out
 
 
@@ -314,42 +413,44 @@ def main():
     Q, q, A, b, G, h = (torch.from_numpy(a).to(dev) for a in P.arrays())
     gx_h = qpgen.upstream(B, n, args.seed + 1)
     gx = torch.from_numpy(gx_h).to(dev)
+
+    def run_steps(opts, steps, warmup):
+        """`steps` timed steps (solve + relax + backward) after `warmup`
+        untimed ones; HIP events on the launch stream around each launch."""
+        def step(timing=None):
+            if timing is not None:
+                timing[0].record()
+            sol = qpx.solve(Q, q, A, b, G, h, opts=opts, work=timing is not None)
+            if timing is not None:
+                timing[1].record()
+            g = qpx.backward(Q, q, A, b, G, h, sol, gx, opts=opts, work=timing is not None)
+            if timing is not None:
+                timing[2].record()
+            return sol, g
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+        t0 = time.perf_counter()
+        sols = [step(evs[k]) for k in range(steps)]
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        fwd = float(np.mean([e[0].elapsed_time(e[1]) for e in evs])) * 1e-3
+        bwd = float(np.mean([e[1].elapsed_time(e[2]) for e in evs])) * 1e-3
+        return sols[-1], wall, fwd, bwd
+
     opts = qpx.make_opts(tol=1e-5, kappa_relax=1e-4)
-
-    def step(timing=None):
-        if timing is not None:
-            timing[0].record()
-        sol = qpx.solve(Q, q, A, b, G, h, opts=opts, work=timing is not None)
-        if timing is not None:
-            timing[1].record()
-        g = qpx.backward(Q, q, A, b, G, h, sol, gx, opts=opts, work=timing is not None)
-        if timing is not None:
-            timing[2].record()
-        return sol, g
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
-    t0 = time.perf_counter()
-    sols = []
-    for k in range(args.steps):
-        sols.append(step(evs[k]))
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    fwd_ms = [e[0].elapsed_time(e[1]) for e in evs]
-    bwd_ms = [e[1].elapsed_time(e[2]) for e in evs]
-    step_ms = [e[0].elapsed_time(e[2]) for e in evs]
-    sol, g = sols[-1]
+    (sol, g), wall, fwd_avg, bwd_avg = run_steps(opts, args.steps, args.warmup)
     status = sol["status"].cpu().numpy()
+    rstatus = g["relaxed"]["status"].cpu().numpy()
     iters = sol["iters"].cpu().numpy()
     work_fwd = float(sol["work"].sum().item())
     work_bwd = float(g["relaxed"]["work"].sum().item())
-    fwd_avg = float(np.mean(fwd_ms)) * 1e-3
-    bwd_avg = float(np.mean(bwd_ms)) * 1e-3
     ms_per_step = wall / args.steps * 1e3
     value = B * args.steps / wall
     achieved = work_fwd / fwd_avg / 1e12
+    solve_k = kernel_name("solve", n, m, p)
+    bwd_k = kernel_name("backward", n, m, p)
 
     out = {
         "metric": METRIC,
@@ -365,12 +466,39 @@ def main():
         "solves_per_s": round(B / fwd_avg, 1),
         "fwd_ms": round(fwd_avg * 1e3, 3), "bwd_ms": round(bwd_avg * 1e3, 3),
         "converged_frac": float(np.mean((status & 0xff) == 0)),
+        "relax_converged_frac": float(np.mean((rstatus & 0xff) == 0)),
         "iters_mean": float(np.mean(iters)), "iters_max": int(np.max(iters)),
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_ALU,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_ALU, 4),
                      "traffic": measured_traffic(fwd_avg),
-                     "kernel": "qp_solve_kernel<256, 2, true> (fused solve, one launch per step)",
+                     "kernel": f"{solve_k} (fused solve, one launch per step)",
                      "launch_ms": round(fwd_avg * 1e3, 3), "peak_packed_fp32": PEAK_ALU_PACKED},
+    }
+    kernels = [
+        roofline_entry(solve_k + " n=50", "alu", achieved, PEAK_ALU, "TFLOP/s", fwd_avg * 1e3),
+        roofline_entry(bwd_k + " n=50", "alu", work_bwd / bwd_avg / 1e12, PEAK_ALU, "TFLOP/s",
+                       bwd_avg * 1e3),
+        roofline_entry(bwd_k + " n=50 (gradient writes, a14)", "hbm",
+                       grad_bytes(B, n, m, p) / bwd_avg / 1e9, PEAK_HBM, "GB/s", bwd_avg * 1e3,
+                       note="gradient bytes written / whole backward launch (relax + adjoint "
+                            "+ writes): a lower bound on the write bandwidth of a14"),
+    ]
+    out["kernels"] = kernels
+    # the same step with FP64-accumulated residuals everywhere (the other
+    # precision policy), for comparison with the FP32-first default
+    (sol64, g64), wall64, f64, b64 = run_steps(qpx.make_opts(tol=1e-5, kappa_relax=1e-4,
+                                                             residual="fp64"),
+                                               max(2, args.steps // 2), 1)
+    out["precision"] = {
+        "default": {"policy": "FP32 residuals; FP64 refinement residuals for QPs whose FP32 "
+                              "refinement stalls",
+                    "solves_per_s": round(B / fwd_avg, 1), "fwd_bwd_per_s": round(value, 1),
+                    "fp64_refinement_frac_fwd": float(np.mean((status >> 16) & 1)),
+                    "fp64_refinement_frac_bwd": float(np.mean((rstatus >> 16) & 1))},
+        "fp64_residual": {"solves_per_s": round(B / f64, 1),
+                          "fwd_bwd_per_s": round(B * max(2, args.steps // 2) / wall64, 1),
+                          "converged_frac": float(np.mean(
+                              (sol64["status"].cpu().numpy() & 0xff) == 0))},
     }
     if not args.no_ablation:
         std = qpx.solve(Q, q, A, b, G, h, form="standard", tol=1e-5)
@@ -379,12 +507,35 @@ def main():
         out["standard_form"] = {"converged_frac": float(np.mean((s2 & 0xff) == 0)),
                                 "nonfinite_or_factor_fail_frac": float(np.mean((s2 & 0xff) >= 2))}
     if not args.no_extra:
+        c3 = timed_config(qpx, torch, qpgen.make_config("differentiation", seed=3))
+        ill = qpgen.make_config("illcond", seed=4)
+        c5 = timed_config(qpx, torch, ill, steps=2, tol=ILL_TOL, kappa_relax=ILL_KAPPA_RELAX)
+        c5b = timed_config(qpx, torch, ill, steps=2, backward=False, tol=ILL_TOL,
+                           assembly="bf16x3")
         out["other_configs"] = {
-            "differentiation n=100 m=200 p=20 B=1024": config_rate(
-                qpx, torch, qpgen.random_feasible(1024, 100, 200, 20, 3)),
-            "ill-conditioned degenerate n=256 m=512 p=32 B=512": config_rate(
-                qpx, torch, qpgen.ill_conditioned(512, 256, 512, 32, 4), steps=1, backward=False),
+            "differentiation n=100 m=200 p=20 B=1024 (tol 1e-5, kappa_relax 1e-4)": c3,
+            f"ill-conditioned degenerate n=256 m=512 p=32 B=512 (tol {ILL_TOL}, "
+            f"kappa_relax {ILL_KAPPA_RELAX}, FP32 matrix-core assembly)": c5,
+            f"ill-conditioned degenerate n=256 m=512 p=32 B=512 (tol {ILL_TOL}, "
+            "BF16x3 split-product assembly + refinement)": c5b,
         }
+        k3s, k3b = kernel_name("solve", 100, 200, 20), kernel_name("backward", 100, 200, 20)
+        k5 = kernel_name("solve", 256, 512, 32)
+        kernels += [
+            roofline_entry(k3s + " n=100", "alu", c3["fwd_flops"] / c3["fwd_ms"] / 1e9,
+                           PEAK_ALU, "TFLOP/s", c3["fwd_ms"]),
+            roofline_entry(k3b + " n=100", "alu", c3["bwd_flops"] / c3["bwd_ms"] / 1e9,
+                           PEAK_ALU, "TFLOP/s", c3["bwd_ms"]),
+            roofline_entry(k3b + " n=100 (gradient writes, a14)", "hbm",
+                           grad_bytes(1024, 100, 200, 20) / c3["bwd_ms"] / 1e6, PEAK_HBM, "GB/s",
+                           c3["bwd_ms"]),
+            roofline_entry(k5 + " n=256 FP32 MFMA assembly", "mfma",
+                           c5["fwd_flops"] / c5["fwd_ms"] / 1e9, PEAK_MFMA_FP32, "TFLOP/s",
+                           c5["fwd_ms"]),
+            roofline_entry(k5 + " n=256 BF16x3 assembly", "mfma",
+                           c5b["fwd_flops"] / c5b["fwd_ms"] / 1e9, PEAK_MFMA_FP32, "TFLOP/s",
+                           c5b["fwd_ms"]),
+        ]
     if not args.no_serving:
         out["serving"] = serving_bench()
     if not args.no_cpu:

@@ -65,6 +65,11 @@ extern "C" {
                                   including the factorisation at the relaxed
                                   point that the gradients use               */
 #define QPX_STAGE_BACKWARD 7   /* adjoint solve / gradients                   */
+/* status[i] bits 16-17: precision events of the QP's run (informational;
+ * the outcome is status[i] & 0xff):                                        */
+#define QPX_USED_FP64_RESIDUAL (1 << 16) /* FP32 refinement stalled; FP64-
+                                            accumulated residuals were used  */
+#define QPX_ASM_FELL_BACK (1 << 17)      /* BF16x3 assembly switched to FP32 */
 
 /* ---- formulations ------------------------------------------------------- */
 #define QPX_BOUNDED 0   /* implicit complementarity, spectrally bounded system
@@ -97,10 +102,11 @@ typedef struct {
   int32_t pc;            /* 1: predictor-corrector centering (default)        */
   float kappa_relax;     /* central-path parameter of the backward (1e-4)     */
   int32_t relax_max_iter;/* Newton iterations of the relaxation (30)          */
-  float relax_tol;       /* stopping tolerance of the relaxation (1e-7); the
-                            residuals are accumulated in FP64, and the
+  float relax_tol;       /* stopping tolerance of the relaxation (1e-6): the
                             gradient of a near-degenerate QP needs a relaxed
-                            point tighter than the solve's tolerance         */
+                            point tighter than the solve's tolerance; the
+                            complementarity term of the implicit forms is
+                            |kappa - kappa_relax| / kappa_relax             */
   int32_t kmax;          /* cap on bordered inequality rows of the bounded
                             factorisation; 0 = automatic: n when the factor
                             fits the workgroup's LDS, else every row (up to
@@ -110,10 +116,34 @@ typedef struct {
   int32_t block;         /* threads per QP: 0 = automatic, or 128/256/512     */
   int32_t assembly;      /* arithmetic of H = Q + G_I' diag(w) G_I, one of
                             QPX_ASM_* below (default QPX_ASM_AUTO)            */
+  float backoff;         /* line-search back-off: step = min(1, backoff *
+                            largest feasible step); 0 = the form's default:
+                            1 (none) for the implicit forms, whose
+                            retraction keeps s, z > 0 (eq. linesearch as
+                            printed), 0.99 for the standard form           */
+  int32_t fp64_residual; /* residual precision, one of QPX_RES_* below
+                            (default QPX_RES_AUTO)                           */
 } qp_opts;
 
-/* Assembly of the (1,1) block of the reduced KKT matrix.  The factorisation,
- * solves and residuals are FP32 (FP64-accumulated residuals) in every mode.
+/* Residual precision.  The method runs in single precision (sections 3
+ * and 5); FP64 enters only as an accumulator of refinement residuals, and
+ * by default only for QPs whose FP32 refinement stalls.
+ *  QPX_RES_AUTO  stopping test and refinement residuals in FP32; a QP whose
+ *                FP32 refinement contracts by less than 1/2 per step
+ *                continues with FP64-accumulated refinement residuals (and
+ *                FP64-accumulated stopping tests) for the rest of its
+ *                solve.  Newton steps refine only regularised or
+ *                split-product factors; the adjoint and equality-only
+ *                solves are always refined (at least two steps).
+ *  QPX_RES_FP64  every residual (stopping test, refinement) accumulated in
+ *                FP64, and every adjoint solve refined twice.
+ *  QPX_RES_FP32  FP32 residuals only; a stalled refinement just stops.     */
+#define QPX_RES_AUTO 0
+#define QPX_RES_FP64 1
+#define QPX_RES_FP32 2
+
+/* Assembly of the (1,1) block of the reduced KKT matrix.  The factorisation
+ * and solves are FP32 in every mode (residuals: see QPX_RES_*).
  *  QPX_ASM_AUTO    QPX_ASM_MFMA_FP32 for the bounded form when n >= 96 and
  *                  the staging buffer fits the workgroup's LDS, else
  *                  QPX_ASM_FP32 (measured: the fastest choice on each side
@@ -186,8 +216,13 @@ int qp_backward(qpx_ctx *ctx, const qp_batch *batch, const qp_opts *opts,
                 const float *dl_dz, qp_grads *grads, qp_out *relaxed,
                 void *stream);
 
-/* Human-readable name of a per-QP status value or return code. */
+/* Human-readable name of a return code (QPX_OK, QPX_PENDING, QPX_ERR_*). */
 const char *qp_status_string(int code);
+
+/* Human-readable description of a per-QP status value (status[i] of
+ * qp_out: the outcome in the low byte, the failing stage above it), e.g.
+ * "non-finite value (stage: predictor)".  Never NULL. */
+const char *qp_result_string(int32_t status);
 
 /* Launch plan the library uses for one problem size (host only; no device
  * call, so it also answers on a machine without a GPU). */

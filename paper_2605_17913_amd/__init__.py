@@ -32,6 +32,8 @@ STAGES = ["none", "scaling", "predictor", "centering", "corrector", "linesearch"
 FORMS = {"bounded": 0, "standard": 1, "condensed": 2}
 # H-block assembly arithmetic (qp_opts.assembly)
 ASSEMBLY = {"auto": 0, "fp32": 1, "bf16x3": 2, "mfma_fp32": 3}
+# residual precision (qp_opts.fp64_residual)
+RESIDUAL = {"auto": 0, "fp64": 1, "fp32": 2}
 
 _c_int32, _c_float, _vp = ctypes.c_int32, ctypes.c_float, ctypes.c_void_p
 
@@ -46,7 +48,7 @@ class _Opts(ctypes.Structure):
                 ("sigma", _c_float), ("pc", _c_int32), ("kappa_relax", _c_float),
                 ("relax_max_iter", _c_int32), ("relax_tol", _c_float), ("kmax", _c_int32),
                 ("delta_reg", _c_float), ("refine_steps", _c_int32), ("block", _c_int32),
-                ("assembly", _c_int32)]
+                ("assembly", _c_int32), ("backoff", _c_float), ("fp64_residual", _c_int32)]
 
 
 class _Out(ctypes.Structure):
@@ -75,7 +77,7 @@ class _Plan(ctypes.Structure):
 
 
 EXPORTS = ["qp_default_opts", "qp_create", "qp_destroy", "qp_solve", "qp_backward",
-           "qp_status_string", "qp_plan_query", "qp_server_create", "qp_serve_submit", "qp_serve_poll",
+           "qp_status_string", "qp_result_string", "qp_plan_query", "qp_server_create", "qp_serve_submit", "qp_serve_poll",
            "qp_serve_stats", "qp_server_destroy"]
 
 _lib = None
@@ -100,6 +102,8 @@ def lib() -> ctypes.CDLL:
                                       ctypes.POINTER(_Out), _vp, _vp, _vp,
                                       ctypes.POINTER(_Grads), ctypes.POINTER(_Out), _vp]
             L.qp_status_string.restype = ctypes.c_char_p
+            L.qp_result_string.argtypes = [_c_int32]
+            L.qp_result_string.restype = ctypes.c_char_p
             L.qp_plan_query.argtypes = [_c_int32, _c_int32, _c_int32, ctypes.POINTER(_Opts),
                                         ctypes.POINTER(_Plan)]
             L.qp_server_create.argtypes = [_vp, ctypes.POINTER(_ServerOpts), ctypes.POINTER(_Opts),
@@ -157,14 +161,20 @@ def default_opts() -> _Opts:
 
 def make_opts(form="bounded", tol=None, max_iter=None, sigma=None, pc=None, kappa_relax=None,
               relax_max_iter=None, relax_tol=None, kmax=None, delta_reg=None, refine_steps=None,
-              block=None, assembly=None) -> _Opts:
+              block=None, assembly=None, backoff=None, residual=None) -> _Opts:
+    """qp_opts with the library defaults, overridden by the given values.
+    assembly: "auto" | "fp32" | "bf16x3" | "mfma_fp32"; residual (the
+    fp64_residual field): "auto" | "fp64" | "fp32"."""
     o = default_opts()
     o.form = FORMS[form] if isinstance(form, str) else int(form)
     if assembly is not None:
         o.assembly = ASSEMBLY[assembly] if isinstance(assembly, str) else int(assembly)
+    if residual is not None:
+        o.fp64_residual = RESIDUAL[residual] if isinstance(residual, str) else int(residual)
     for k, v in dict(tol=tol, max_iter=max_iter, sigma=sigma, kappa_relax=kappa_relax,
                      relax_max_iter=relax_max_iter, relax_tol=relax_tol, kmax=kmax,
-                     delta_reg=delta_reg, refine_steps=refine_steps, block=block).items():
+                     delta_reg=delta_reg, refine_steps=refine_steps, block=block,
+                     backoff=backoff).items():
         if v is not None:
             setattr(o, k, v)
     if pc is not None:
@@ -260,9 +270,10 @@ def backward(Q, q, A, b, G, h, sol, dl_dx, dl_dy=None, dl_dz=None, *, opts: _Opt
                    z=torch.empty(B, m, **f32), s=torch.empty(B, m, **f32),
                    status=torch.empty(B, dtype=torch.int32, device=Q.device),
                    iters=torch.empty(B, dtype=torch.int32, device=Q.device),
+                   res=torch.empty(B, **f32),
                    work=torch.empty(B, dtype=torch.float64, device=Q.device))
         ro = _Out(_ptr(rel["x"]), _ptr(rel["y"]), _ptr(rel["z"]), _ptr(rel["s"]),
-                  _ptr(rel["status"]), _ptr(rel["iters"]), None, _ptr(rel["work"]))
+                  _ptr(rel["status"]), _ptr(rel["iters"]), _ptr(rel["res"]), _ptr(rel["work"]))
     _check(lib().qp_backward(_context(dev), ctypes.byref(st), ctypes.byref(o), ctypes.byref(so),
                              _ptr(gx), _ptr(gy), _ptr(gz), ctypes.byref(sg),
                              ctypes.byref(ro) if ro is not None else None, _stream(dev)),
@@ -273,26 +284,66 @@ def backward(Q, q, A, b, G, h, sol, dl_dx, dl_dy=None, dl_dz=None, *, opts: _Opt
 
 
 class QPFunction(torch.autograd.Function):
-    """x* = argmin QP(Q, q, A, b, G, h); backward = relax + implicit
-    function theorem at kappa_relax.  Options are passed as a dict."""
+    """x* = argmin QP(Q, q, A, b, G, h) as a differentiable function of the
+    problem data (paper sections 2.3 and 5): the forward pass is Algorithm 1,
+    the backward pass relaxes to kappa_relax (Algorithm 2) and applies the
+    implicit-function-theorem product of Algorithm 3, all in the library's
+    kernels.  A, b (p = 0) and G, h (m = 0) may be None.  Returns (x, status);
+    status (int32 [B], not differentiable) is the per-QP status word of the
+    solve.  With check=True a QP that did not converge in the solve, or
+    whose relaxation did not converge in the backward pass, raises QPError.
+    `options` is a dict of make_opts keyword arguments."""
 
     @staticmethod
-    def forward(ctx, Q, q, A, b, G, h, options):
+    def forward(ctx, Q, q, A, b, G, h, options, check):
         options = dict(options or {})
         sol = solve(Q, q, A, b, G, h, **options)
+        status = sol["status"]
+        if check:
+            bad = torch.nonzero((status & 0xFF) != 0).flatten()
+            if bad.numel():
+                raise QPError(f"{bad.numel()} QP(s) did not converge in the solve, first "
+                              f"{bad[0].item()}: {result_string(int(status[bad[0]].item()))}")
         ctx.options = options
+        ctx.check = check
+        ctx.has_A, ctx.has_G = A is not None, G is not None
+        ctx.dtypes = [None if t is None else t.dtype for t in (Q, q, A, b, G, h)]
         ctx.save_for_backward(Q, q, A, b, G, h, sol["x"], sol["y"], sol["z"], sol["s"])
-        return sol["x"]
+        ctx.mark_non_differentiable(status)
+        return sol["x"], status
 
     @staticmethod
-    def backward(ctx, gx):
+    def backward(ctx, gx, _gstatus):
         Q, q, A, b, G, h, x, y, z, s = ctx.saved_tensors
-        g = backward(Q, q, A, b, G, h, dict(x=x, y=y, z=z, s=s), gx.contiguous(), **ctx.options)
-        return g["Q"], g["q"], g["A"], g["b"], g["G"], g["h"], None
+        need = ctx.needs_input_grad[:6]
+        if not any(need):
+            return (None,) * 8
+        g = backward(Q, q, A, b, G, h, dict(x=x, y=y, z=z, s=s),
+                     gx.to(torch.float32).contiguous(), relaxed=ctx.check, **ctx.options)
+        if ctx.check:
+            rst = g["relaxed"]["status"]
+            bad = torch.nonzero((rst & 0xFF) != 0).flatten()
+            if bad.numel():
+                raise QPError(f"{bad.numel()} QP(s) did not converge in the relaxation, first "
+                              f"{bad[0].item()}: {result_string(int(rst[bad[0]].item()))}")
+        out = []
+        for k, key in enumerate(("Q", "q", "A", "b", "G", "h")):
+            present = ctx.dtypes[k] is not None
+            out.append(g[key].to(ctx.dtypes[k]) if (present and need[k]) else None)
+        return (*out, None, None)
 
 
-def qp_layer(Q, q, A, b, G, h, **options):
-    return QPFunction.apply(Q, q, A, b, G, h, options)
+def qp_layer(Q, q, A=None, b=None, G=None, h=None, *, return_status=False, check=True,
+             **options):
+    """Differentiable batched QP layer: x*(Q, q, A, b, G, h) (see QPFunction).
+    return_status=True also returns the per-QP status words."""
+    x, status = QPFunction.apply(Q, q, A, b, G, h, options, check)
+    return (x, status) if return_status else x
+
+
+def result_string(status: int) -> str:
+    """Human-readable description of a per-QP status word."""
+    return lib().qp_result_string(int(status)).decode()
 
 
 class Server:

@@ -1,6 +1,6 @@
 // Host side of the C-ABI declared in include/qpx.h: argument validation,
 // launch configuration, workspace management.  Every step of the solver runs
-// in the HIP kernels of qp_kernels.hip.
+// in the HIP kernels of qp_kernel_impl.hpp.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -25,6 +25,7 @@ int set_device(const qpx_ctx *ctx) {
 // demand (previous contents are not kept; the device is synchronised before
 // a buffer that may still be in use is freed).
 int ensure_ws(qpx_ctx *ctx, size_t bytes, hipStream_t st) {
+  if (bytes == 0) return QPX_OK;
   if (ctx->ws_used && ctx->ws_stream != st &&
       hipStreamSynchronize(ctx->ws_stream) != hipSuccess)
     return QPX_ERR_HIP;
@@ -44,6 +45,11 @@ int ensure_ws(qpx_ctx *ctx, size_t bytes, hipStream_t st) {
   return QPX_OK;
 }
 
+// Global workspace of a launch: the factors when they do not fit LDS.
+size_t ws_bytes(const qpk::Plan &pl, int B) {
+  return pl.m_in_lds ? 0 : (size_t)B * pl.ws_stride * sizeof(float);
+}
+
 int check_batch(const qp_batch *bt) {
   if (!bt) return QPX_ERR_ARG;
   if (bt->B < 0 || bt->n < 1 || bt->m < 0 || bt->p < 0 || bt->p >= bt->n) return QPX_ERR_ARG;
@@ -61,6 +67,8 @@ int check_opts(const qp_opts &o) {
   if (!(o.delta_reg >= 0.f)) return QPX_ERR_ARG;
   if (o.kmax < 0 || o.refine_steps < 0) return QPX_ERR_ARG;
   if (o.assembly < QPX_ASM_AUTO || o.assembly > QPX_ASM_MFMA_FP32) return QPX_ERR_ARG;
+  if (!(o.backoff >= 0.f && o.backoff <= 1.f)) return QPX_ERR_ARG;
+  if (o.fp64_residual < QPX_RES_AUTO || o.fp64_residual > QPX_RES_FP32) return QPX_ERR_ARG;
   return QPX_OK;
 }
 
@@ -74,6 +82,8 @@ void fill_common(qpk::Params &P, const qp_batch *bt, const qp_opts &o, const qpk
   P.tol = o.tol; P.sigma = o.sigma; P.kappa_relax = o.kappa_relax;
   P.relax_tol = o.relax_tol; P.delta_reg = o.delta_reg;
   P.asm_mode = pl.amode;
+  P.rmode = o.fp64_residual;
+  P.backoff = o.backoff > 0.f ? o.backoff : (o.form == QPX_STANDARD ? 0.99f : 1.f);
   P.ws = pl.m_in_lds ? nullptr : ctx->ws;
   P.ws_stride = pl.ws_stride;
 }
@@ -130,12 +140,14 @@ int qp_default_opts(qp_opts *o) {
   o->pc = 1;
   o->kappa_relax = 1e-4f;
   o->relax_max_iter = 30;
-  o->relax_tol = 1e-7f;
+  o->relax_tol = 1e-6f;
   o->kmax = 0;
   o->delta_reg = 0.f;
   o->refine_steps = 0;
   o->block = 0;
   o->assembly = QPX_ASM_AUTO;
+  o->backoff = 0.f;
+  o->fp64_residual = QPX_RES_AUTO;
   return QPX_OK;
 }
 
@@ -173,7 +185,7 @@ int qp_plan_query(int32_t n, int32_t m, int32_t p, const qp_opts *opts, qp_plan 
   plan->factor_in_lds = pl.m_in_lds ? 1 : 0;
   plan->assembly = pl.amode == 1 ? QPX_ASM_BF16X3 : (pl.amode == 2 ? QPX_ASM_MFMA_FP32 : QPX_ASM_FP32);
   plan->lds_bytes = pl.lds;
-  plan->workspace_bytes = (size_t)pl.ws_stride * sizeof(float);
+  plan->workspace_bytes = pl.m_in_lds ? 0 : (size_t)pl.ws_stride * sizeof(float);
   return QPX_OK;
 }
 
@@ -194,9 +206,7 @@ int qp_solve(qpx_ctx *ctx, const qp_batch *bt, const qp_opts *opts, qp_out *out,
   if ((rc = set_device(ctx))) return rc;
   hipStream_t st = static_cast<hipStream_t>(stream);
   std::lock_guard<std::mutex> lk(ctx->mu);
-  if (!pl.m_in_lds) {
-    if ((rc = ensure_ws(ctx, (size_t)bt->B * pl.ws_stride * sizeof(float), st))) return rc;
-  }
+  if ((rc = ensure_ws(ctx, ws_bytes(pl, bt->B), st))) return rc;
   qpk::Params P;
   fill_common(P, bt, o, pl, ctx);
   P.x = out->x; P.y = out->y; P.z = out->z; P.s = out->s;
@@ -227,9 +237,7 @@ int qp_backward(qpx_ctx *ctx, const qp_batch *bt, const qp_opts *opts, const qp_
   if ((rc = set_device(ctx))) return rc;
   hipStream_t st = static_cast<hipStream_t>(stream);
   std::lock_guard<std::mutex> lk(ctx->mu);
-  if (!pl.m_in_lds) {
-    if ((rc = ensure_ws(ctx, (size_t)bt->B * pl.ws_stride * sizeof(float), st))) return rc;
-  }
+  if ((rc = ensure_ws(ctx, ws_bytes(pl, bt->B), st))) return rc;
   qpk::Params P;
   fill_common(P, bt, o, pl, ctx);
   P.x = sol->x; P.y = sol->y; P.z = sol->z; P.s = sol->s;
@@ -238,7 +246,8 @@ int qp_backward(qpx_ctx *ctx, const qp_batch *bt, const qp_opts *opts, const qp_
   P.dG = grads->dG; P.dh = grads->dh;
   if (relaxed) {
     P.rx = relaxed->x; P.ry = relaxed->y; P.rz = relaxed->z; P.rs = relaxed->s;
-    P.rstatus = relaxed->status; P.riters = relaxed->iters; P.work = relaxed->work;
+    P.rstatus = relaxed->status; P.riters = relaxed->iters; P.res = relaxed->res;
+    P.work = relaxed->work;
   }
   P.mode = qpk::kBackward;
   QPK_PHASES("backward", P, st, true);
@@ -249,17 +258,35 @@ int qp_backward(qpx_ctx *ctx, const qp_batch *bt, const qp_opts *opts, const qp_
 
 const char *qp_status_string(int code) {
   switch (code) {
-    case QPX_OK: return "ok / converged";
-    case QPX_PENDING: return "pending / max_iter";
-    case QPX_NONFINITE: return "non-finite value";
-    case QPX_FACTOR_FAIL: return "factorisation failed (non-positive pivot)";
+    case QPX_OK: return "ok";
+    case QPX_PENDING: return "pending";
     case QPX_ERR_ARG: return "invalid argument";
     case QPX_ERR_OOM: return "out of memory";
     case QPX_ERR_HIP: return "HIP runtime error";
     case QPX_ERR_STATE: return "invalid state";
     case QPX_ERR_UNSUPPORTED: return "unsupported size";
-    default: return "unknown";
+    default: return "unknown return code";
   }
+}
+
+const char *qp_result_string(int32_t status) {
+  static const char *outcome[4] = {"converged", "iteration limit reached", "non-finite value",
+                                   "factorisation failed (non-positive pivot)"};
+  static const char *stage[8] = {"", "scaling", "predictor", "centering", "corrector",
+                                 "line search", "relax", "backward"};
+  // every (outcome, stage) pair as one static string
+  static char table[4][8][80];
+  static std::once_flag once;
+  std::call_once(once, [] {
+    for (int o = 0; o < 4; ++o)
+      for (int g = 0; g < 8; ++g) {
+        if (g == 0) std::snprintf(table[o][g], sizeof(table[o][g]), "%s", outcome[o]);
+        else std::snprintf(table[o][g], sizeof(table[o][g]), "%s (stage: %s)", outcome[o], stage[g]);
+      }
+  });
+  const int o = status & 0xff, g = (status >> 8) & 0xff;
+  if (status < 0 || o > 3 || g > 7 || (status >> 18) != 0) return "unknown per-QP status";
+  return table[o][g];
 }
 
 }  // extern "C"

@@ -1,5 +1,6 @@
 // Internal interface between the host C-ABI (qp_api.cpp) and the HIP
-// kernels (qp_kernels.hip).  Not installed; not part of the public ABI.
+// kernels (qp_kernel_impl.hpp, instantiated by qp_inst_*.hip and dispatched
+// by qp_launch.hip).  Not installed; not part of the public ABI.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stddef.h>
@@ -38,7 +39,9 @@ struct Params {
   // options
   int32_t form, max_iter, pc, kb, relax_max_iter, refine;
   int32_t asm_mode;  // H-block assembly: 0 FP32 VALU, 1 BF16x3 MFMA, 2 FP32 MFMA
+  int32_t rmode;     // residual precision (qp_opts.fp64_residual)
   float tol, sigma, kappa_relax, relax_tol, delta_reg;
+  float backoff;     // line-search back-off, resolved per form
   // factor storage in global memory (when it does not fit LDS)
   float *ws;
   int64_t ws_stride;  // floats per QP
@@ -52,11 +55,15 @@ struct Params {
 // server's arena; `state` holds x, y, z, s contiguously.
 struct SlotDesc {
   int32_t n, m, p, kb;      // sizes; kb = cap on bordered inequality rows
-  int32_t flags, pad_[3];   // flags: bit0 = fresh (run the initialisation),
+  int32_t flags;            // bit0 = fresh (run the initialisation),
                             // bits 1-2 = H-block assembly mode (Params::asm_mode)
+  int32_t budget;           // Newton iterations this step may take
+  int32_t pad_[2];
   const float *Q, *q, *A, *b, *G, *h;
-  float *state;             // x[n] y[p] z[m] s[m]
+  float *state;             // x[n] y[p] z[m] s[m], then one word of sticky
+                            // arithmetic state (assembly mode, FP64 residuals)
   float *ws;                // factor storage (global) or NULL
+  float *out;               // copy of x y z s for the host (this launch's staging)
   int32_t *status, *iters;  // per slot
   float *res;
 };

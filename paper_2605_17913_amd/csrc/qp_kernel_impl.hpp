@@ -76,6 +76,10 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) f4v lf4;
 typedef __attribute__((address_space(1))) float gf;
 typedef __attribute__((address_space(1))) f4v gf4;
+// LDS pointer type of a residual accumulator (FP32 or FP64).
+template <class AT> struct LdsT;
+template <> struct LdsT<float> { typedef __attribute__((address_space(3))) float type; };
+template <> struct LdsT<double> { typedef __attribute__((address_space(3))) double type; };
 template <class F> struct Vec4;
 template <> struct Vec4<lf> { typedef lf4 type; };
 template <> struct Vec4<gf> { typedef gf4 type; };
@@ -219,6 +223,7 @@ struct Layout {
 };
 
 __host__ __device__ inline int al4(int a) { return (a + 3) & ~3; }
+
 
 __host__ __device__ inline Layout make_layout(int n, int m, int p, int kb, bool m_lds, int T) {
   Layout L;
@@ -709,26 +714,27 @@ QPD void signed_solve_wave(const MF *M, int N, int npos, const lf *dinv, lf *r, 
   }
 }
 
-// FP64-accumulated out[j] (+)= sum_i R[i*ld + j] x[i]; barriers inside.
-template <int T, class RF, class XF>
-QPD float coldot_d(const RF *R, int ld, int rows, int cols, const XF *x, ldd *out, bool add,
-                   ldd *part) {
+// out[j] (+)= sum_i R[i*ld + j] x[i], accumulated in AT (FP32 or FP64);
+// barriers inside.
+template <int T, class AT, class RF, class XF>
+QPD float coldot_d(const RF *R, int ld, int rows, int cols, const XF *x,
+                   typename LdsT<AT>::type *out, bool add, typename LdsT<AT>::type *part) {
   float mx = 0.f;  // largest |column sum| this thread produced
   const int cw = cols <= 64 ? 64 : (cols <= 128 ? (T >= 128 ? 128 : 64) : (T >= 256 ? 256 : T));
   const int groups = T / cw;
   const int g = threadIdx.x / cw, jl = threadIdx.x % cw;
   for (int jb = 0; jb < cols; jb += cw) {
     const int j = jb + jl;
-    double acc = 0.0;
+    AT acc = 0;
     if (j < cols) {
-      // independent loads first (several in flight), then the FP64 chain
+      // independent loads first (several in flight), then the accumulation chain
 #pragma unroll 8
-      for (int i = g; i < rows; i += groups) acc = fma((double)R[(size_t)i * ld + j], (double)x[i], acc);
+      for (int i = g; i < rows; i += groups) acc = fma((AT)R[(size_t)i * ld + j], (AT)x[i], acc);
     }
     part[threadIdx.x] = acc;
     __syncthreads();
     if (g == 0 && j < cols) {
-      double s = 0.0;
+      AT s = 0;
       for (int gg = 0; gg < groups; ++gg) s += part[gg * cw + jl];
       out[j] = add ? out[j] + s : s;
       mx = fmaxf(mx, fabsf((float)s));
@@ -739,52 +745,55 @@ QPD float coldot_d(const RF *R, int ld, int rows, int cols, const XF *x, ldd *ou
 }
 
 // The products the residuals need, in one pass over Q, G and A (each n
-// columns wide), accumulated in FP64: gx = G x and ax = A x (row dots) and
+// columns wide), accumulated in AT (FP32, or FP64 for the residuals of the
+// FP64 policy and of escalated refinements): gx = G x and ax = A x (row dots) and
 // rt = Q'x + G'z + A'y (column sums).  16 lanes share a row (columns
 // jb + sub + 16k, k < 4, in blocks of 64), T/16 rows at a time, with the
 // loads of several rows in flight before their arithmetic, so each input
 // element is read once.  The column sums of each matrix are reduced across
-// row groups (shuffles inside a wave, then `part`, T doubles, across
+// row groups (shuffles inside a wave, then `part`, T values, across
 // waves); their largest magnitudes, which scale the residuals, come back in
 // mq, mg, ma (per-thread partial maxima).  Without gcols, G contributes
 // its row dots only (z is not read).  No LDS pointer is tested against
 // NULL: LDS address 0 is a valid address.  Barriers inside.
-template <int T>
+template <int T, class AT>
 QPD void kkt_matvecs(const gf *Q, const gf *G, const gf *A, int n, int m, int p, const lf *x,
-                     const lf *z, bool gcols, const lf *y, ldd *gx, ldd *ax, ldd *rt, ldd *part,
-                     float &mq, float &mg, float &ma) {
+                     const lf *z, bool gcols, const lf *y, typename LdsT<AT>::type *gx,
+                     typename LdsT<AT>::type *ax, typename LdsT<AT>::type *rt,
+                     typename LdsT<AT>::type *part, float &mq, float &mg, float &ma) {
+  typedef typename LdsT<AT>::type la;
   constexpr int RG = T / 16;
   const int tid = threadIdx.x, sub = tid & 15, grp = tid >> 4, wid = tid >> 6;
   mq = mg = ma = 0.f;
   for (int jb = 0; jb < n; jb += 64) {
-    double xv[4], cq[4], cg[4], ca[4];
+    AT xv[4], cq[4], cg[4], ca[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int j = jb + sub + 16 * k;
-      xv[k] = j < n ? (double)x[j] : 0.0;
-      cq[k] = cg[k] = ca[k] = 0.0;
+      xv[k] = j < n ? (AT)x[j] : (AT)0;
+      cq[k] = cg[k] = ca[k] = 0;
     }
     // rows of R weighted by w (if cols) into c; with dots, also the row dots
     // with x into out
-    auto sweep = [&](const gf *R, int rows, const lf *w, bool cols, ldd *out, bool dots,
-                     double(&c)[4]) {
+    auto sweep = [&](const gf *R, int rows, const lf *w, bool cols, la *out, bool dots,
+                     AT(&c)[4]) {
 #pragma unroll 4
       for (int i0 = 0; i0 < rows; i0 += RG) {
         const int i = i0 + grp;
         float e[4] = {0.f, 0.f, 0.f, 0.f};
-        double wi = 0.0;
+        AT wi = 0;
         if (i < rows) {
           const gf *Ri = R + (size_t)i * n + jb + sub;
 #pragma unroll
           for (int k = 0; k < 4; ++k)
             if (jb + sub + 16 * k < n) e[k] = Ri[16 * k];
-          if (cols) wi = (double)w[i];
+          if (cols) wi = (AT)w[i];
         }
-        double d = 0.0;
+        AT d = 0;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-          c[k] = fma((double)e[k], wi, c[k]);
-          if (dots) d = fma((double)e[k], xv[k], d);
+          c[k] = fma((AT)e[k], wi, c[k]);
+          if (dots) d = fma((AT)e[k], xv[k], d);
         }
         if (dots) {
 #pragma unroll
@@ -797,7 +806,7 @@ QPD void kkt_matvecs(const gf *Q, const gf *G, const gf *A, int n, int m, int p,
     if (m) sweep(G, m, z, gcols, gx, true, cg);
     if (p) sweep(A, p, y, true, ax, true, ca);
     // column sums across the row groups, one matrix at a time
-    auto reduce = [&](double(&c)[4], bool first, float &mx) {
+    auto reduce = [&](AT(&c)[4], bool first, float &mx) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         c[k] += __shfl_xor(c[k], 16, 64);
@@ -809,7 +818,7 @@ QPD void kkt_matvecs(const gf *Q, const gf *G, const gf *A, int n, int m, int p,
       }
       __syncthreads();
       if (tid < 64 && jb + tid < n) {
-        double sum = 0.0;
+        AT sum = 0;
 #pragma unroll
         for (int w = 0; w < T / 64; ++w) sum += part[w * 64 + tid];
         rt[jb + tid] = first ? sum : rt[jb + tid] + sum;
@@ -847,6 +856,9 @@ struct Ctx {
   lf *stg;    // matrix-core assembly staging (aliases u0 .. dd)
   int amode;  // H-block assembly: 0 FP32 VALU, 1 BF16x3 MFMA, 2 FP32 MFMA
   int dyn;    // bounded form: regularise degenerate factorisations (R13)
+  int rmode;  // residual precision: 0 FP32 first (FP64 refinement after a
+              // stall), 1 FP64 residuals everywhere, 2 FP32 only
+  float bo;   // line-search back-off factor (1 = none)
   __attribute__((address_space(3))) long long *pt;
 };
 
@@ -874,6 +886,8 @@ QPD void init_ctx(Ctx<MF> &C, lf *sm, const Layout &L, MF *Mptr) {
   C.stg = sm + L.stg;
   C.amode = 0;
   C.dyn = 1;
+  C.rmode = 0;
+  C.bo = 1.f;
   C.pt = nullptr;  // set by profiling builds
 }
 
@@ -899,42 +913,48 @@ QPD Ctx<MF> uctx(const Ctx<MF> &I) {
   C.mz = rflp(I.mz);
   C.dd = rflp(I.dd);
   C.role = rflp(I.role); C.bidx = rflp(I.bidx); C.elist = rflp(I.elist); C.iflag = rflp(I.iflag);
-  C.stg = rflp(I.stg); C.amode = rfl(I.amode); C.dyn = rfl(I.dyn);
+  C.stg = rflp(I.stg); C.amode = rfl(I.amode); C.dyn = rfl(I.dyn); C.rmode = rfl(I.rmode); C.bo = rflf(I.bo);
   C.pt = rflp(I.pt);
   return C;
 }
 
 // Residuals at (x, y, z, s) and, for the bounded form, (v, kappa).
 // Returns the scaled residual measure (uniform); `bad` = a non-finite value
-// was seen.  complementarity: max(z s) (solve) or max|z s - kr| / kr (relax).
-template <int T, class CT>
+// was seen.  Complementarity: max(z s) in the solve; in the relaxation
+// (kr > 0) |kappa - kr| / kr for the implicit forms, whose retraction keeps
+// every z_i s_i equal to kappa (per-row products differ from it only by
+// rounding, about 1e-7 relative in FP32), and max|z s - kr| / kr for the
+// standard form.  The matrix-vector products are accumulated in AT: FP32 by
+// default, FP64 under the FP64 residual policy (the FP32 iterate is exact in
+// FP64, so that residual is limited only by the iterate's rounding).
+template <int T, class AT, class CT>
 QPK_PHASE float residuals(CT &Cin_, bool bounded, float kappa, float kr, bool *bad) {
   CT C = uctx(Cin_);
   bounded = rfl(bounded); kappa = rflf(kappa); kr = rflf(kr);
+  typedef typename LdsT<AT>::type la;
   const int n = C.n, m = C.m, p = C.p, tid = threadIdx.x;
-  // matrix-vector products accumulated in FP64 (the FP32 iterate is exact
-  // in FP64, so the residual is limited only by the iterate's rounding)
-  // one FP64 accumulator for Qx + G'z + A'y; the pieces' norms are taken
-  // as they are produced
-  ldd *gxd = C.dd, *axd = C.dd + m, *rtd = C.dd + m + p;
-  ldd *pd = reinterpret_cast<ldd *>(C.part);
+  // one accumulator for Qx + G'z + A'y; the pieces' norms are taken as they
+  // are produced
+  la *gxd = reinterpret_cast<la *>(C.dd), *axd = gxd + m, *rtd = gxd + m + p;
+  la *pd = reinterpret_cast<la *>(C.part);
   enum { RT, QX, QQ, GZ, AY, RI, GX, SS, HH, RE, AX, BB, RZS, ZZ, CC, NF, NK };
   float mx[NK];
 #pragma unroll
   for (int k = 0; k < NK; ++k) mx[k] = 0.f;
-  kkt_matvecs<T>(C.Q, C.G, C.A, n, m, p, C.x, C.z, true, C.y, gxd, axd, rtd, pd, mx[QX],
-                 mx[GZ], mx[AY]);
+  kkt_matvecs<T, AT>(C.Q, C.G, C.A, n, m, p, C.x, C.z, true, C.y, gxd, axd, rtd, pd, mx[QX],
+                     mx[GZ], mx[AY]);
+  const bool man = bounded && kr > 0.f;  // relaxation of an implicit form
   for (int i = tid; i < n; i += T) {
-    const float r = (float)(rtd[i] + (double)C.q[i]);
+    const float r = (float)(rtd[i] + (AT)C.q[i]);
     C.rt[i] = r;
     mx[RT] = fmaxf(mx[RT], fabsf(r));
     mx[QQ] = fmaxf(mx[QQ], fabsf(C.q[i]));
     if (!finitef(r)) mx[NF] = 1.f;
   }
   for (int i = tid; i < m; i += T) {
-    const double gx = gxd[i];
+    const AT gx = gxd[i];
     const float si = C.s[i], zi = C.z[i];
-    const float r = (float)(gx + (double)si - (double)C.h[i]);
+    const float r = (float)(gx + (AT)si - (AT)C.h[i]);
     C.ri[i] = r;
     mx[RI] = fmaxf(mx[RI], fabsf(r));
     mx[GX] = fmaxf(mx[GX], fabsf((float)gx));
@@ -951,12 +971,12 @@ QPK_PHASE float residuals(CT &Cin_, bool bounded, float kappa, float kr, bool *b
     }
     mx[RZS] = fmaxf(mx[RZS], fmaxf(fabsf(rz), fabsf(rs)));
     const float zs = zi * si;
-    mx[CC] = fmaxf(mx[CC], kr > 0.f ? fabsf(zs - kr) / kr : zs);
+    if (!man) mx[CC] = fmaxf(mx[CC], kr > 0.f ? fabsf(zs - kr) / kr : zs);
     if (!finitef(r) || !finitef(zs) || !finitef(rz) || !finitef(rs)) mx[NF] = 1.f;
   }
   for (int i = tid; i < p; i += T) {
-    const double ax = axd[i];
-    const float r = (float)(ax - (double)C.b[i]);
+    const AT ax = axd[i];
+    const float r = (float)(ax - (AT)C.b[i]);
     C.re[i] = r;
     mx[RE] = fmaxf(mx[RE], fabsf(r));
     mx[AX] = fmaxf(mx[AX], fabsf((float)ax));
@@ -968,7 +988,7 @@ QPK_PHASE float residuals(CT &Cin_, bool bounded, float kappa, float kr, bool *b
   const float ri_s = m ? mx[RI] / (1.f + fmaxf(mx[GX], fmaxf(mx[SS], mx[HH]))) : 0.f;
   const float re_s = p ? mx[RE] / (1.f + fmaxf(mx[AX], mx[BB])) : 0.f;
   const float rzs = m ? mx[RZS] / (1.f + fmaxf(mx[ZZ], mx[SS])) : 0.f;
-  const float cc = m ? mx[CC] : 0.f;
+  const float cc = m ? (man ? fabsf(kappa - kr) / kr : mx[CC]) : 0.f;
   *bad = mx[NF] != 0.f;
   return fmaxf(fmaxf(rt_s, ri_s), fmaxf(fmaxf(re_s, rzs), cc));
 }
@@ -1385,60 +1405,97 @@ QPK_PHASE void solve2(CT &Cin_, int N, bool both) {
 // holds z/s or 1),
 // Dl = D/E on bounded border rows and 0 on equality rows, against the
 // operator WITHOUT any regularisation, with the residual w - K u
-// accumulated in FP64 from the original Q, G, A.  Each step solves for the
-// correction with the existing factor (one wave) and adds it.  A step whose
-// residual is not smaller than the previous one is taken back and ends the
-// refinement.  Returns the largest ratio of successive residual max-norms
-// (0 after a single step): above 1/2 the factor is too coarse a
-// preconditioner for this system.
+// accumulated in AT (FP32, or FP64 once a QP's FP32 refinement stalled)
+// from the original Q, G, A.  Each step solves for the correction with the
+// existing factor (one wave) and adds it.  A step whose residual is not
+// smaller than the previous one is taken back and ends the refinement.
+// Returns the contraction of the first correction (residual max-norm after
+// it over the one before; 0 after a single step, kBig for a non-finite
+// residual): above 1/2 the factor is too coarse a preconditioner in this
+// arithmetic.
 constexpr float kRefineSlow = 0.5f;
-template <int T, int RPL, class CT>
+
+// out = w - K u (sub) or K u, for the augmented operator of refine (below),
+// accumulated in AT from the original Q, G, A and rounded to FP32.
+// Barriers inside; u must be visible to all threads on entry.
+template <int T, class AT, class CT>
+QPD void kkt_apply(CT &C, int nb, bool bounded, const lf *w, const lf *u, lf *out, bool sub) {
+  typedef typename LdsT<AT>::type la;
+  const int n = C.n, m = C.m, p = C.p, tid = threadIdx.x;
+  la *gx = reinterpret_cast<la *>(C.dd), *ax = gx + m, *phi = gx + m + p, *kx = gx + 2 * m + p;
+  la *pd = reinterpret_cast<la *>(C.part);
+  // G u, A u and Q'u_x + A'u_y in one pass; then G' phi, which needs G u
+  float unused[3];
+  kkt_matvecs<T, AT>(C.Q, C.G, C.A, n, m, p, u, u, false, u + n + nb, gx, ax, kx, pd, unused[0],
+                     unused[1], unused[2]);
+  for (int i = tid; i < m; i += T) {
+    const int k = C.role[i];
+    const AT wi = bounded ? (AT)C.E[i] / (AT)C.D[i] : (AT)C.E[i];
+    phi[i] = k >= 0 ? (AT)u[n + k] : wi * gx[i];
+  }
+  __syncthreads();
+  if (m) coldot_d<T, AT>(C.G, n, m, n, phi, kx, true, pd);
+  const AT sg = sub ? (AT)-1 : (AT)1;
+  for (int j = tid; j < n; j += T) out[j] = (float)((sub ? (AT)w[j] : (AT)0) + sg * kx[j]);
+  for (int k = tid; k < nb; k += T) {
+    const int i = C.bidx[k];
+    const AT dl = bounded ? (AT)C.D[i] / (AT)C.E[i] : (AT)0;
+    out[n + k] = (float)((sub ? (AT)w[n + k] : (AT)0) + sg * (gx[i] - dl * (AT)u[n + k]));
+  }
+  for (int a = tid; a < p; a += T)
+    out[n + nb + a] = (float)((sub ? (AT)w[n + nb + a] : (AT)0) + sg * ax[a]);
+  __syncthreads();
+}
+
+// Largest |r_j| over j < N (kBig if any entry is not finite); uniform.
+template <int T>
+QPD float maxnorm(const lf *r, int N, lf *red) {
+  float mx[2] = {0.f, 0.f};
+  for (int j = threadIdx.x; j < N; j += T) {
+    const float a = fabsf(r[j]);
+    mx[0] = fmaxf(mx[0], a);
+    if (!(a <= FLT_MAX)) mx[1] = 1.f;
+  }
+  block_reduce<T, OpMax, 2>(mx, red);
+  return mx[1] != 0.f ? kBig : mx[0];
+}
+
+// Iterative refinement of a solution u of the augmented system
+//   [[H, C'], [C, -Dl]] u = w,  H = Q + G_I' diag(wts_I) G_I,  C = [G_B; A],
+// wts = E/D (bounded form) or E (standard form / initialisation, where E
+// holds z/s or 1),
+// Dl = D/E on bounded border rows and 0 on equality rows, against the
+// operator WITHOUT any regularisation, with the residual w - K u
+// accumulated in AT (FP32, or FP64 once a QP's FP32 refinement stalled)
+// from the original Q, G, A.  Each step solves for the correction with the
+// existing factor (one wave) and adds it; the residual after each
+// correction is checked, and a correction that did not make it smaller is
+// taken back and ends the refinement.  Returns the contraction of the first
+// correction (residual max-norm after it over the one before; kBig for a
+// non-finite residual): above 1/2 the factor is too coarse a
+// preconditioner in this arithmetic.
+template <int T, int RPL, class AT, class CT>
 QPK_PHASE float refine(CT &Cin_, int nb, bool bounded, const lf *w, lf *u, int steps) {
   CT C = uctx(Cin_);
   nb = rfl(nb); bounded = rfl(bounded); w = rflp(w); u = rflp(u); steps = rfl(steps);
-  const int n = C.n, m = C.m, p = C.p, tid = threadIdx.x, N = n + nb + p;
-  ldd *gx = C.dd, *ax = C.dd + m, *phi = C.dd + m + p, *kx = C.dd + 2 * m + p;
-  ldd *pd = reinterpret_cast<ldd *>(C.part);
+  const int n = C.n, p = C.p, tid = threadIdx.x, N = n + nb + p;
   lf *r = C.rr;
-  float prev = 0.f, worst = 0.f;
-  for (int it = 0; it < steps; ++it) {
-    // G u, A u and Q'u_x + A'u_y in one pass; then G' phi, which needs G u
-    float unused[3];
-    kkt_matvecs<T>(C.Q, C.G, C.A, n, m, p, u, u, false, u + n + nb, gx, ax, kx, pd, unused[0],
-                   unused[1], unused[2]);
-    for (int i = tid; i < m; i += T) {
-      const int k = C.role[i];
-      const double wi = bounded ? (double)C.E[i] / (double)C.D[i] : (double)C.E[i];
-      phi[i] = k >= 0 ? (double)u[n + k] : wi * gx[i];
-    }
-    __syncthreads();
-    if (m) coldot_d<T>(C.G, n, m, n, phi, kx, true, pd);
-    for (int j = tid; j < n; j += T) r[j] = (float)((double)w[j] - kx[j]);
-    for (int k = tid; k < nb; k += T) {
-      const int i = C.bidx[k];
-      const double dl = bounded ? (double)C.D[i] / (double)C.E[i] : 0.0;
-      r[n + k] = (float)((double)w[n + k] - (gx[i] - dl * (double)u[n + k]));
-    }
-    for (int a = tid; a < p; a += T) r[n + nb + a] = (float)((double)w[n + nb + a] - ax[a]);
-    __syncthreads();
-    // residual max-norm (a non-finite residual counts as no progress)
-    float mx[2] = {0.f, 0.f};
-    for (int j = tid; j < N; j += T) {
-      const float a = fabsf(r[j]);
-      mx[0] = fmaxf(mx[0], a);
-      if (!(a <= FLT_MAX)) mx[1] = 1.f;
-    }
-    block_reduce<T, OpMax, 2>(mx, C.red);
-    const float nrm = mx[1] != 0.f ? kBig : mx[0];
+  float prev = 0.f, first = 0.f;
+  for (int it = 0; it <= steps; ++it) {
+    kkt_apply<T, AT>(C, nb, bounded, w, u, r, true);
+    const float nrm = maxnorm<T>(r, N, C.red);
     if (it > 0) {
-      worst = fmaxf(worst, prev > 0.f ? nrm / prev : 0.f);
+      if (it == 1) first = prev > 0.f ? nrm / prev : 0.f;
       if (!(nrm < prev)) {
         // the last correction did not help: take it back and stop
         for (int j = tid; j < N; j += T) u[j] -= C.rd[j];
         __syncthreads();
         break;
       }
+    } else if (nrm == 0.f) {
+      break;  // exact already
     }
+    if (it == steps) break;
     prev = nrm;
     if (threadIdx.x < 64) signed_solve_wave<RPL>(C.M, N, n, C.dinv, r, C.mz);
     __syncthreads();
@@ -1448,7 +1505,39 @@ QPK_PHASE float refine(CT &Cin_, int nb, bool bounded, const lf *w, lf *u, int s
     }
     __syncthreads();
   }
-  return worst;
+  return first;
+}
+
+// Residual precision of the refinement (qp_opts.fp64_residual): refine in
+// FP32; under the automatic policy a QP whose FP32 refinement contracts by
+// less than kRefineSlow per step continues in FP64 residuals, and keeps
+// them for the rest of its solve (iflag[5]).  Returns the contraction of
+// the arithmetic that ran last.
+template <int T, int RPL, class CT>
+QPD float refine_policy(CT &C, int nb, bool bounded, const lf *w, lf *u, int steps) {
+  float q;
+  if (C.rmode == 1 || C.iflag[5]) {
+    q = refine<T, RPL, double>(C, nb, bounded, w, u, steps);
+  } else {
+    q = refine<T, RPL, float>(C, nb, bounded, w, u, steps);
+    if (C.rmode == 0 && !(q <= kRefineSlow)) {
+      __syncthreads();
+      if (threadIdx.x == 0) C.iflag[5] = 1;
+      __syncthreads();
+      q = refine<T, RPL, double>(C, nb, bounded, w, u, steps);
+    }
+  }
+  return q;
+}
+
+// Refinement steps of a solve with a factor of the exact operator (neither
+// regularised nor assembled from split products): at least `min_steps`
+// where the answer needs it (the adjoint solve, the equality-only solve; an
+// FP32 factor's backward error grows with the system size, so FP32
+// residuals still improve these).
+QPD int plain_refine_steps(int rmode, int user_steps, int min_steps) {
+  (void)rmode;
+  return max(user_steps, min_steps);
 }
 
 
@@ -1633,6 +1722,14 @@ constexpr int SG_NONE = 0, SG_SCAL = 1, SG_PRED = 2, SG_CENT = 3, SG_CORR = 4, S
 
 QPD int mkstatus(int st, int stage) { return st | (stage << 8); }
 
+// Precision events of a QP's run, reported in status bits 16-17: FP64
+// refinement residuals were needed; the split-product assembly fell back to
+// FP32.
+template <class CT>
+QPD int precision_bits(const CT &C, int amode0) {
+  return (C.iflag[5] ? 1 << 16 : 0) | (amode0 == 1 && C.iflag[3] != 1 ? 1 << 17 : 0);
+}
+
 // ---------------------------------------------------------------------------
 // Initialisation (CVXOPT convention): solve [[Q+G'G, A'], [A, 0]] [x; y] =
 // [-q + G'h; b], zt = Gx - h, s = -zt, z = zt, each shifted positive.
@@ -1659,7 +1756,9 @@ QPK_PHASE bool initialize(CT &Cin_, double &work, bool dyn) {
   for (int i = tid; i < m; i += T) C.role[i] = -1;
   __syncthreads();
   solve2<T, RPL>(C, N, false);
-  if (m == 0) refine<T, RPL>(C, 0, false, C.w0, C.u0, 2);
+  // without inequalities this solve is the answer
+  const int nref0 = m == 0 ? plain_refine_steps(C.rmode, 0, 2) : 0;
+  if (nref0) refine_policy<T, RPL>(C, 0, false, C.w0, C.u0, nref0);
   for (int i = tid; i < n; i += T) C.x[i] = C.u0[i];
   for (int k = tid; k < p; k += T) C.y[k] = C.u0[n + k];
   __syncthreads();
@@ -1685,7 +1784,7 @@ QPK_PHASE bool initialize(CT &Cin_, double &work, bool dyn) {
   __syncthreads();
   const double dn = n, dm = m, dN = N;
   work += dm * dn * (dn + 1.0) + dN * dN * dN / 3.0 + 2.0 * dN * dN + 4.0 * dm * dn;
-  if (m == 0) work += 2.0 * (2.0 * dN * dN + 2.0 * dn * dn);  // two refinement steps
+  work += nref0 * (2.0 * dN * dN + 2.0 * dn * dn);  // refinement steps
   return ok;
 }
 
@@ -1725,7 +1824,8 @@ QPK_PHASE int newton_bounded(CT &Cin_, float &kappa, int kt_mode, float sigma, f
     make_dinv<T>(C, N);
     rhs_bounded<T>(C, nb, kappa, nullptr, nullptr, nullptr, false);
     QPK_PT(C, PH_RHS);
-    const int nref = (reg || C.amode == 1) ? max(refine_steps, 2) : refine_steps;
+    const int nref = (reg || C.amode == 1) ? max(refine_steps, 2)
+                                           : plain_refine_steps(C.rmode, refine_steps, 0);
     if (nref) {
       for (int j = tid; j < N; j += T) { C.w0[j] = C.u0[j]; C.w1[j] = C.u1[j]; }
       __syncthreads();
@@ -1733,8 +1833,8 @@ QPK_PHASE int newton_bounded(CT &Cin_, float &kappa, int kt_mode, float sigma, f
     solve2<T, RPL>(C, N, true);
     QPK_PT(C, PH_SOLVE);
     if (nref) {
-      const float q0 = refine<T, RPL>(C, nb, true, C.w0, C.u0, nref);
-      const float q1 = refine<T, RPL>(C, nb, true, C.w1, C.u1, nref);
+      const float q0 = refine_policy<T, RPL>(C, nb, true, C.w0, C.u0, nref);
+      const float q1 = refine_policy<T, RPL>(C, nb, true, C.w1, C.u1, nref);
       work += 2.0 * nref * (2.0 * dN * dN + 4.0 * dm * dn + 2.0 * dn * dn + 4.0 * dp * dn);
       if (C.amode == 1 && !(fmaxf(q0, q1) <= kRefineSlow)) {
         C.amode = 2;
@@ -1800,7 +1900,7 @@ QPK_PHASE int newton_bounded(CT &Cin_, float &kappa, int kt_mode, float sigma, f
   }
   block_reduce<T, OpMin, 2>(mn, C.red);
   if (mn[1] < 0.f) { *stage = kt_mode == 2 ? SG_RELAX : SG_CORR; return ST_NONFIN; }
-  const float alpha = mn[0];
+  const float alpha = fminf(1.f, C.bo * mn[0]);
   if (!(alpha > 0.f)) { *stage = SG_LS; return ST_NONFIN; }
   // step on (x, y, v, kappa), then retract z, s
   for (int i = tid; i < n; i += T) C.x[i] += alpha * fmaf(kt, C.u1[i], C.u0[i]);
@@ -1915,7 +2015,7 @@ QPK_PHASE int newton_standard(CT &Cin_, float mu, int kt_mode, float kr, float d
   }
   block_reduce<T, OpMin, 2>(mn, C.red);
   if (mn[1] < 0.f) { *stage = kt_mode == 2 ? SG_RELAX : SG_CORR; return ST_NONFIN; }
-  const float alpha = fminf(1.f, 0.99f * mn[0]);
+  const float alpha = fminf(1.f, C.bo * mn[0]);
   if (!(alpha > 0.f) || !finitef(alpha)) { *stage = SG_LS; return ST_NONFIN; }
   for (int i = tid; i < n; i += T) C.x[i] += alpha * C.u0[i];
   for (int k = tid; k < p; k += T) C.y[k] += alpha * C.u0[n + k];
@@ -1925,6 +2025,34 @@ QPK_PHASE int newton_standard(CT &Cin_, float mu, int kt_mode, float kr, float d
   }
   __syncthreads();
   return ST_CONV;
+}
+
+// Without inequalities (m = 0) the refined KKT solve of the initialisation
+// is the answer, and its accuracy is that of a direct solve: the backward
+// error max(|r_t| / (1 + | |Q||x| + |q| + |A'||y| |), |r_e| / (1 + | |A||x|
+// + |b| |)) (infinity norms) measures it.  The scaled residual of the
+// general test divides by the largest term instead, which for a solution
+// with heavy cancellation (|Q||x| >> |Qx|) lies below what any float32
+// vector attains.  Uses r_t, r_e from residuals(); uniform result.
+template <int T, class CT>
+QPD float direct_backward_error(CT &C) {
+  const int n = C.n, p = C.p, tid = threadIdx.x;
+  float mx[4] = {0.f, 0.f, 0.f, 0.f};  // |r_t|, its scale, |r_e|, its scale
+  for (int j = tid; j < n; j += T) {
+    float a = fabsf(C.q[j]);
+    for (int i = 0; i < n; ++i) a = fmaf(fabsf(C.Q[(size_t)i * n + j]), fabsf(C.x[i]), a);
+    for (int k = 0; k < p; ++k) a = fmaf(fabsf(C.A[(size_t)k * n + j]), fabsf(C.y[k]), a);
+    mx[0] = fmaxf(mx[0], fabsf(C.rt[j]));
+    mx[1] = fmaxf(mx[1], a);
+  }
+  for (int k = tid; k < p; k += T) {
+    float a = fabsf(C.b[k]);
+    for (int j = 0; j < n; ++j) a = fmaf(fabsf(C.A[(size_t)k * n + j]), fabsf(C.x[j]), a);
+    mx[2] = fmaxf(mx[2], fabsf(C.re[k]));
+    mx[3] = fmaxf(mx[3], a);
+  }
+  block_reduce<T, OpMax, 4>(mx, C.red);
+  return fmaxf(mx[0] / (1.f + mx[1]), p ? mx[2] / (1.f + mx[3]) : 0.f);
 }
 
 // Newton loop shared by the solve, the relaxation and the serving step.
@@ -1946,7 +2074,11 @@ QPD int newton_loop(CT &C, bool bounded, int max_iter, float tol, int kt_mode, f
     block_reduce<T, OpSum, 1>(sm, C.red);
     float kappa = m ? sm[0] / (float)m : 0.f;
     bool bad = false;
-    res = residuals<T>(C, bounded, kappa, kt_mode == 2 ? kr : 0.f, &bad);
+    // FP64 residuals under the FP64 policy, and for a QP whose refinement
+    // has already needed FP64 (FP32 cannot resolve its residuals either)
+    const bool r64 = C.rmode == 1 || (C.rmode == 0 && C.iflag[5] != 0);
+    res = r64 ? residuals<T, double>(C, bounded, kappa, kt_mode == 2 ? kr : 0.f, &bad)
+              : residuals<T, float>(C, bounded, kappa, kt_mode == 2 ? kr : 0.f, &bad);
     QPK_PT(C, PH_RESID);
     if (bad || !finitef(res)) {
       status = ST_NONFIN;
@@ -1955,7 +2087,13 @@ QPD int newton_loop(CT &C, bool bounded, int max_iter, float tol, int kt_mode, f
       break;
     }
     if (res < tol) { status = ST_CONV; iters = it; break; }
-    if (it >= max_iter || m == 0) { status = ST_MAXIT; iters = it; break; }
+    if (m == 0) {
+      res = direct_backward_error<T>(C);
+      status = res < tol ? ST_CONV : ST_MAXIT;
+      iters = it;
+      break;
+    }
+    if (it >= max_iter) { status = ST_MAXIT; iters = it; break; }
     int st;
     if (bounded)
       st = newton_bounded<T, RPL>(C, kappa, kt_mode, sigma, kr, delta_reg, refine_steps, work, &stage);
@@ -2019,10 +2157,9 @@ QPK_PHASE bool adjoint(CT &Cin_, bool bounded, const gf *gx, const gf *gy, const
     for (int i = tid; i < m; i += T) C.E[i] = C.t1[i];
   __syncthreads();
   const int N = n + nb + p;
-  const int nref = refine_steps + 2;
   const double dn = n, dN = N;
   const double wfac = (double)ne * dn * (dn + 1.0) + dN * dN * dN / 3.0 + 2.0 * dN * dN + 8.0 * m * dn;
-  const double wref = nref * (2.0 * dN * dN + 2.0 * dn * dn + 8.0 * m * dn + 4.0 * p * dn);
+  const double wstep = 2.0 * dN * dN + 2.0 * dn * dn + 8.0 * m * dn + 4.0 * p * dn;
   bool ok = false;
   if (bounded) {
     C.amode = rfl(C.iflag[3]);
@@ -2037,14 +2174,18 @@ QPK_PHASE bool adjoint(CT &Cin_, bool bounded, const gf *gx, const gf *gy, const
       }
       bool reg = false;
       ok = factor_bounded<T, RPL>(C, nb, ne, C.t1, delta_reg, &reg, floor);
-      work += wfac + wref;
+      // the adjoint solve gives the gradient directly: a regularised or
+      // split-product factor is always refined against the exact operator
+      const int nref = (reg || C.amode == 1) ? max(refine_steps, 2)
+                                             : plain_refine_steps(C.rmode, refine_steps, 2);
+      work += wfac + nref * wstep;
       if (!ok) break;
       make_dinv<T>(C, N);
       rhs_bounded<T>(C, nb, kappa, gx, gz, gy, true);
       for (int j = tid; j < N; j += T) C.w0[j] = C.u0[j];
       __syncthreads();
       solve2<T, RPL>(C, N, false);
-      const float q = refine<T, RPL>(C, nb, true, C.w0, C.u0, nref);
+      const float q = nref ? refine_policy<T, RPL>(C, nb, true, C.w0, C.u0, nref) : 0.f;
       if (C.amode == 1 && !(q <= kRefineSlow)) {
         C.amode = 2;
         if (tid == 0) C.iflag[3] = 2;
@@ -2064,7 +2205,8 @@ QPK_PHASE bool adjoint(CT &Cin_, bool bounded, const gf *gx, const gf *gy, const
   } else {
     assemble<T>(C, nb, ne, C.t1, false, 0.f);
     ok = signed_cholesky<T, RPL>(C.M, N, n, C.iflag, false);
-    work += wfac + wref;
+    const int nref = plain_refine_steps(C.rmode, refine_steps, 2);
+    work += wfac + nref * wstep;
     if (!ok) return false;
     make_dinv<T>(C, N);
     // standard: [H A'; A 0][a; c] = [-gx - G' W gz; -gy], dz = W (G a + gz)
@@ -2079,7 +2221,7 @@ QPK_PHASE bool adjoint(CT &Cin_, bool bounded, const gf *gx, const gf *gy, const
     for (int k = tid; k < p; k += T) C.u0[n + k] = C.w0[n + k] = gy ? -gy[k] : 0.f;
     __syncthreads();
     solve2<T, RPL>(C, N, false);
-    refine<T, RPL>(C, 0, false, C.w0, C.u0, nref);
+    if (nref) refine_policy<T, RPL>(C, 0, false, C.w0, C.u0, nref);
     if (m) {
       const lf *xv[1] = {C.u0};
       lf *o[1] = {C.t0};
@@ -2192,6 +2334,7 @@ QPD void qp_body(const Params &P) {
   C.h_g = (const gf *)hp;
   if constexpr (MODE == kServe) C.amode = (P.desc[qi].flags >> 1) & 3;
   else C.amode = P.asm_mode;
+  const int amode0 = C.amode;
   const int refine = P.refine;
   const int tid = threadIdx.x;
   // per-QP assembly mode for the Newton steps (a BF16x3 QP may fall back)
@@ -2201,6 +2344,11 @@ QPD void qp_body(const Params &P) {
   // regularisation); form 1 is the standard explicit IPM
   const bool bounded = P.form != 1;
   C.dyn = P.form == 0;
+  C.rmode = P.rmode;
+  C.bo = P.backoff;
+  if (tid == 0) {
+    C.iflag[5] = 0;  // refinement residuals start in FP32
+  }
 #ifdef QPK_PHASE_TIMING
   __shared__ long long pt_acc[PH_N];
   C.pt = (__attribute__((address_space(3))) long long *)pt_acc;
@@ -2214,10 +2362,14 @@ QPD void qp_body(const Params &P) {
   float res = 0.f;
   int status;
   if constexpr (MODE == kServe) {
-    // resume one resident QP for at most max_iter Newton iterations; the
-    // iterate (x, y, z, s) persists in the slot's state between steps
+    // resume one resident QP for at most d.budget Newton iterations; the
+    // iterate (x, y, z, s) and the QP's arithmetic state (its assembly
+    // arithmetic after any fallback, FP64 refinement residuals) persist in
+    // the slot's state between steps, so the split into steps does not
+    // change what is computed
     const SlotDesc &d = P.desc[qi];
     gf *st = (gf *)d.state;
+    const int sticky = n + p + 2 * m;
     bool ok = true;
     if (d.flags & 1) {
       ok = initialize<T, RPL>(C, work, C.dyn != 0);
@@ -2228,12 +2380,17 @@ QPD void qp_body(const Params &P) {
         C.z[i] = st[n + p + i];
         C.s[i] = st[n + p + m + i];
       }
+      if (tid == 0) {
+        const int f = __float_as_int(st[sticky]);
+        C.iflag[3] = f & 3;
+        C.iflag[5] = (f >> 2) & 1;
+      }
       __syncthreads();
     }
     if (!ok) {
       status = mkstatus(ST_FACT, SG_PRED);
     } else {
-      status = newton_loop<T, RPL>(C, bounded, P.max_iter, P.tol, P.pc ? 0 : 1, P.sigma, 0.f,
+      status = newton_loop<T, RPL>(C, bounded, d.budget, P.tol, P.pc ? 0 : 1, P.sigma, 0.f,
                                    P.delta_reg, refine, work, iters, res);
     }
     for (int i = tid; i < n; i += T) st[i] = C.x[i];
@@ -2242,8 +2399,17 @@ QPD void qp_body(const Params &P) {
       st[n + p + i] = C.z[i];
       st[n + p + m + i] = C.s[i];
     }
+    gf *out = (gf *)d.out;
+    for (int i = tid; i < n; i += T) out[i] = C.x[i];
+    for (int k = tid; k < p; k += T) out[n + k] = C.y[k];
+    for (int i = tid; i < m; i += T) {
+      out[n + p + i] = C.z[i];
+      out[n + p + m + i] = C.s[i];
+    }
+    __syncthreads();
+    if (tid == 0) st[sticky] = __int_as_float((C.iflag[3] & 3) | ((C.iflag[5] & 1) << 2));
     if (tid == 0) {
-      *d.status = status;
+      *d.status = status | precision_bits(C, amode0);
       *d.iters = iters;
       *d.res = res;
     }
@@ -2262,8 +2428,9 @@ QPD void qp_body(const Params &P) {
     if (p && P.y) for (int k = tid; k < p; k += T) ((gf *)P.y)[qi * p + k] = C.y[k];
     if (m && P.z) for (int i = tid; i < m; i += T) ((gf *)P.z)[qi * m + i] = C.z[i];
     if (m && P.s) for (int i = tid; i < m; i += T) ((gf *)P.s)[qi * m + i] = C.s[i];
+    __syncthreads();
     if (tid == 0) {
-      P.status[qi] = status;
+      P.status[qi] = status | precision_bits(C, amode0);
       if (P.iters) P.iters[qi] = iters;
       if (P.res) P.res[qi] = res;
       if (P.work) P.work[qi] = work;
@@ -2281,6 +2448,9 @@ QPD void qp_body(const Params &P) {
     __syncthreads();
     status = newton_loop<T, RPL>(C, bounded, P.relax_max_iter, P.relax_tol, 2, 0.f, P.kappa_relax,
                                  P.delta_reg, refine, work, iters, res);
+    // without inequalities there is nothing to relax: the relaxed point is
+    // the solution (whose own status reports its accuracy)
+    if (m == 0 && (status & 0xff) == ST_MAXIT) status = mkstatus(ST_CONV, SG_NONE);
     const gf *gx = (const gf *)P.gx + qi * (size_t)n;
     const gf *gy = P.gy ? (const gf *)P.gy + qi * (size_t)p : nullptr;
     const gf *gz = P.gz ? (const gf *)P.gz + qi * (size_t)m : nullptr;
@@ -2295,9 +2465,11 @@ QPD void qp_body(const Params &P) {
     if (P.ry && p) for (int k = tid; k < p; k += T) ((gf *)P.ry)[qi * p + k] = C.y[k];
     if (P.rz && m) for (int i = tid; i < m; i += T) ((gf *)P.rz)[qi * m + i] = C.z[i];
     if (P.rs && m) for (int i = tid; i < m; i += T) ((gf *)P.rs)[qi * m + i] = C.s[i];
+    __syncthreads();
     if (tid == 0) {
-      if (P.rstatus) P.rstatus[qi] = status;
+      if (P.rstatus) P.rstatus[qi] = status | precision_bits(C, amode0);
       if (P.riters) P.riters[qi] = iters;
+      if (P.res) P.res[qi] = res;
       if (P.work) P.work[qi] = work;
     }
   }

@@ -1,20 +1,32 @@
 // Serving runtime: continuous batching of single QPs of uneven sizes.
 //
-// A scheduler thread owns one HIP stream and a device arena.  Each step it
+// A scheduler thread owns a device arena and kLanes streams ("lanes").
+// Resident QPs are grouped into size-class buckets (threads per QP,
+// rows-per-lane variant, factor placement).  Whenever a lane is idle, the
+// scheduler
 //  1. admits queued requests while a slot is free and the arena has room for
 //     the request's footprint (inputs + iterate + factor storage if the
-//     factor does not fit LDS), copying the request's data into the arena;
-//  2. launches the serving kernel once per size bucket (threads per QP,
-//     rows-per-lane variant, factor placement); every resident QP resumes
-//     its Newton loop from the iterate kept in the arena for at most
-//     `iters_per_step` iterations (a fresh QP first runs the initialisation);
-//  3. reads back the per-slot status and retires finished QPs (converged,
-//     failed, or out of iterations), copying their solution to the host and
-//     freeing their arena space and slot for the next admissions.
-// Requests that arrive while others are on the device join at the next step,
-// so work of different requests overlaps on the GPU.  Each QP's arithmetic
-// is independent of the others in its launch, and resuming from a stored
-// iterate repeats exactly what an uninterrupted solve computes, so a request
+//     factor does not fit LDS);
+//  2. launches the serving kernel on the lane for one bucket of resident QPs
+//     that are not in flight (the bucket holding the longest-waiting QP):
+//     the new requests' data are uploaded first on the same stream, every QP
+//     resumes its Newton loop from the iterate kept in the arena for a
+//     bounded number of iterations (a fresh QP first runs the
+//     initialisation), and the kernel also writes each QP's iterate to the
+//     lane's staging buffer, which comes back to the host with the status
+//     words in the same stream;
+//  3. when a lane's launch has completed (polled with an event), retires
+//     the QPs of that launch that finished (converged, failed, or out of
+//     iterations), copying their solution from the staging buffer, and
+//     frees their arena space and slot.
+// Lanes complete independently: a bucket of small QPs is retired, refilled
+// and launched again while a bucket of large ones is still running, so a
+// small request's latency does not wait for the largest size class.
+// Requests that arrive while others are on the device join at the next
+// launch of their bucket.  Each QP's arithmetic is independent of the others
+// in its launch, its per-launch iteration budget depends only on its own
+// size and progress, and resuming from the stored iterate and arithmetic
+// state repeats exactly what an uninterrupted solve computes, so a request
 // gives the same result alone and in a mix.
 #include <hip/hip_runtime.h>
 
@@ -52,8 +64,10 @@ struct Request {
   double t_submit = 0, t_admit = 0, t_done = 0;
   int status = 0, iters = 0;
   bool done = false;
-  bool fresh = false;  // admitted this step: the kernel runs the initialisation
-  // arena placement (floats offsets relative to the request's block)
+  bool fresh = false;      // not yet launched: the kernel runs the initialisation
+  bool in_flight = false;  // part of a launch that has not completed
+  uint64_t order = 0;      // admission order (oldest bucket first)
+  // arena placement (byte offsets relative to the request's block)
   size_t off = 0, bytes = 0;
   size_t o_Q, o_q, o_A, o_b, o_G, o_h, o_state, o_ws;
 };
@@ -102,7 +116,7 @@ void layout_request(Request *r) {
   size_t o = 0;
   auto take = [&](size_t floats) { size_t b = o; o += al256(floats * 4); return b; };
   r->o_Q = take(n * n); r->o_q = take(n); r->o_A = take(p * n); r->o_b = take(p);
-  r->o_G = take(m * n); r->o_h = take(m); r->o_state = take(n + p + 2 * m);
+  r->o_G = take(m * n); r->o_h = take(m); r->o_state = take(n + p + 2 * m + 1);
   r->o_ws = r->plan.m_in_lds ? 0 : take((size_t)r->plan.ws_stride);
   r->bytes = o;
 }
@@ -112,11 +126,24 @@ struct Bucket {
   int rpl;
   bool mlds;
 };
-bool operator<(const Bucket &a, const Bucket &b) {
-  if (a.threads != b.threads) return a.threads < b.threads;
-  if (a.rpl != b.rpl) return a.rpl < b.rpl;
-  return a.mlds < b.mlds;
-}
+
+// Floats of a request's iterate (x, y, z, s), and of its place in a lane's
+// staging buffer (64-float aligned).
+size_t state_floats(int n, int m, int p) { return (size_t)n + p + 2 * (size_t)m; }
+size_t staged_floats(const Request *r) { return (state_floats(r->n, r->m, r->p) + 63) & ~size_t(63); }
+
+// One stream with the buffers of the launch in flight on it.
+struct Lane {
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  qpk::SlotDesc *d_desc = nullptr, *h_desc = nullptr;
+  int32_t *d_status = nullptr, *d_iters = nullptr, *h_status = nullptr, *h_iters = nullptr;
+  float *d_res = nullptr;
+  float *d_out = nullptr, *h_out = nullptr;  // staging of the iterates
+  std::vector<Request *> batch;              // the launch in flight (launch order)
+  std::vector<size_t> out_off;               // each QP's place in the staging buffer
+  bool busy = false;
+};
 
 }  // namespace
 
@@ -124,185 +151,191 @@ struct qpx_server {
   qpx_ctx *ctx = nullptr;
   qp_server_opts o{};
   qp_opts so{};
-  hipStream_t stream = nullptr;
-  // size-class buckets of one device step run concurrently on the main
-  // stream and these (all at the default priority); events order them after
-  // the descriptor upload and before the status download
-  static constexpr int kSide = 3;
-  hipStream_t side[kSide] = {};
-  hipEvent_t ev_ready = nullptr, ev_done[kSide] = {};
+  // lanes run at the default stream priority
+  static constexpr int kLanes = 4;
+  Lane lane[kLanes];
+  size_t staging = 0;  // staging buffer floats per lane
   char *arena_dev = nullptr;
   Arena arena;
-  qpk::SlotDesc *d_desc = nullptr, *h_desc = nullptr;
-  int32_t *d_status = nullptr, *d_iters = nullptr, *h_status = nullptr, *h_iters = nullptr;
-  float *d_res = nullptr, *h_res = nullptr;
   std::mutex mu;
   std::condition_variable cv;
   std::deque<Request *> pending;
   std::unordered_map<uint64_t, Request *> by_ticket;
-  std::vector<Request *> active;
+  std::vector<Request *> active;  // resident (admitted, not retired)
   std::thread th;
   std::atomic<bool> stop{false};
   std::atomic<int> error{0};
-  uint64_t next_ticket = 1, admitted = 0, completed = 0;
+  uint64_t next_ticket = 1, admitted = 0, completed = 0, admit_order = 0;
   int peak = 0;
 };
 
 namespace {
+
+Bucket bucket_of(const Request *r) {
+  const int N = r->n + r->plan.kb + r->p;
+  return Bucket{r->plan.threads, (N + 63) / 64, r->plan.m_in_lds};
+}
+
+// Launch one bucket of idle resident QPs on lane L.  Called with S->mu held
+// (reads the active list).  Returns false if nothing was launched.
+bool launch_bucket(qpx_server *S, Lane &L) {
+  // the bucket of the longest-waiting idle QP
+  const Request *oldest = nullptr;
+  for (const Request *r : S->active)
+    if (!r->in_flight && (!oldest || r->order < oldest->order)) oldest = r;
+  if (!oldest) return false;
+  const Bucket bk = bucket_of(oldest);
+  std::vector<Request *> cand;
+  for (Request *r : S->active) {
+    if (r->in_flight) continue;
+    const Bucket b = bucket_of(r);
+    if (b.threads == bk.threads && b.rpl == bk.rpl && b.mlds == bk.mlds) cand.push_back(r);
+  }
+  std::sort(cand.begin(), cand.end(),
+            [](const Request *a, const Request *b) { return a->order < b->order; });
+  // oldest first, as many as the staging buffer holds (at least one)
+  L.batch.clear();
+  L.out_off.clear();
+  size_t lds = 0, used = 0;
+  for (Request *r : cand) {
+    const size_t f = staged_floats(r);
+    if (!L.batch.empty() && used + f > S->staging) break;
+    L.batch.push_back(r);
+    L.out_off.push_back(used);
+    used += f;
+    lds = std::max(lds, r->plan.lds);
+  }
+  // data of QPs launched for the first time, then the descriptors
+  for (Request *r : L.batch) {
+    r->in_flight = true;
+    if (!r->fresh) continue;
+    char *base = S->arena_dev + r->off;
+    const size_t n = r->n, m = r->m, p = r->p;
+    const float *src = r->data.data();
+    auto put = [&](size_t o, size_t floats) {
+      if (floats) (void)hipMemcpyAsync(base + o, src, floats * 4, hipMemcpyHostToDevice, L.stream);
+      src += floats;
+    };
+    put(r->o_Q, n * n); put(r->o_q, n); put(r->o_A, p * n); put(r->o_b, p);
+    put(r->o_G, m * n); put(r->o_h, m);
+  }
+  for (int k = 0; k < (int)L.batch.size(); ++k) {
+    const Request *r = L.batch[k];
+    char *base = S->arena_dev + r->off;
+    qpk::SlotDesc &d = L.h_desc[k];
+    std::memset(&d, 0, sizeof(d));
+    d.n = r->n; d.m = r->m; d.p = r->p; d.kb = r->plan.kb;
+    d.flags = (r->fresh ? 1 : 0) | (r->plan.amode << 1);
+    // small size classes run more iterations per launch (their launches end
+    // well before the largest class's); the iterate persists between
+    // launches, so how iterations are split over them does not change them.
+    // No QP runs past max_iter in total.
+    const int mult = bk.rpl <= 1 ? 4 : (bk.rpl <= 2 ? 2 : 1);
+    d.budget = std::min(S->o.iters_per_step * mult, S->so.max_iter - r->iters);
+    d.Q = (const float *)(base + r->o_Q); d.q = (const float *)(base + r->o_q);
+    d.A = r->p ? (const float *)(base + r->o_A) : nullptr;
+    d.b = r->p ? (const float *)(base + r->o_b) : nullptr;
+    d.G = r->m ? (const float *)(base + r->o_G) : nullptr;
+    d.h = r->m ? (const float *)(base + r->o_h) : nullptr;
+    d.state = (float *)(base + r->o_state);
+    d.ws = r->plan.m_in_lds ? nullptr : (float *)(base + r->o_ws);
+    d.out = L.d_out + L.out_off[k];
+    d.status = L.d_status + k; d.iters = L.d_iters + k; d.res = L.d_res + k;
+  }
+  const int cnt = (int)L.batch.size();
+  (void)hipMemcpyAsync(L.d_desc, L.h_desc, cnt * sizeof(qpk::SlotDesc), hipMemcpyHostToDevice,
+                       L.stream);
+  qpk::Params P;
+  std::memset(&P, 0, sizeof(P));
+  P.n = 64 * bk.rpl;  // dispatch only: rows-per-lane variant
+  P.form = S->so.form; P.max_iter = S->so.max_iter; P.pc = S->so.pc;
+  P.tol = S->so.tol; P.sigma = S->so.sigma; P.delta_reg = S->so.delta_reg;
+  P.refine = S->so.refine_steps;
+  P.rmode = S->so.fp64_residual;
+  P.backoff = S->so.backoff > 0.f ? S->so.backoff : (S->so.form == QPX_STANDARD ? 0.99f : 1.f);
+  P.desc = L.d_desc;
+  P.mode = qpk::kServe;
+  if (qpk::launch(P, bk.threads, bk.mlds, lds, cnt, L.stream) != hipSuccess) S->error = QPX_ERR_HIP;
+  (void)hipMemcpyAsync(L.h_status, L.d_status, cnt * 4, hipMemcpyDeviceToHost, L.stream);
+  (void)hipMemcpyAsync(L.h_iters, L.d_iters, cnt * 4, hipMemcpyDeviceToHost, L.stream);
+  (void)hipMemcpyAsync(L.h_out, L.d_out, used * 4, hipMemcpyDeviceToHost, L.stream);
+  (void)hipEventRecord(L.done, L.stream);
+  L.busy = true;
+  return true;
+}
+
+// Retire the finished QPs of lane L's completed launch.  Called with S->mu.
+void complete_lane(qpx_server *S, Lane &L) {
+  const double t = now_s();
+  std::vector<Request *> keep;
+  keep.reserve(S->active.size());
+  for (int k = 0; k < (int)L.batch.size(); ++k) {
+    Request *r = L.batch[k];
+    r->in_flight = false;
+    r->fresh = false;
+    r->iters += L.h_iters[k];
+    const int st = L.h_status[k] & 0xff;
+    if (st == 1 && r->iters < S->so.max_iter) continue;  // still running
+    r->status = L.h_status[k];
+    const float *src = L.h_out + L.out_off[k];
+    r->sol.assign(src, src + state_floats(r->n, r->m, r->p));
+    S->arena.release(r->off, r->bytes);
+    r->t_done = t;
+    r->done = true;
+    std::vector<float>().swap(r->data);
+    ++S->completed;
+  }
+  for (Request *r : S->active)
+    if (!r->done) keep.push_back(r);
+  S->active.swap(keep);
+  L.batch.clear();
+  L.busy = false;
+}
 
 void scheduler(qpx_server *S) {
   if (hipSetDevice(S->ctx->device) != hipSuccess) {
     S->error = QPX_ERR_HIP;
     return;
   }
-  std::vector<Request *> fresh;
   for (;;) {
-    fresh.clear();
-    {
-      std::unique_lock<std::mutex> lk(S->mu);
-      while ((int)S->active.size() < S->o.max_slots && !S->pending.empty()) {
-        Request *r = S->pending.front();
-        size_t off;
-        if (!S->arena.alloc(r->bytes, &off)) break;  // wait for memory to free up
-        S->pending.pop_front();
-        r->off = off;
-        r->t_admit = now_s();
-        r->fresh = true;
-        S->active.push_back(r);
-        fresh.push_back(r);
-        ++S->admitted;
+    bool progress = false;
+    std::unique_lock<std::mutex> lk(S->mu);
+    // retire completed launches
+    for (Lane &L : S->lane) {
+      if (!L.busy) continue;
+      const hipError_t q = hipEventQuery(L.done);
+      if (q == hipErrorNotReady) continue;
+      if (q != hipSuccess) S->error = QPX_ERR_HIP;
+      complete_lane(S, L);
+      progress = true;
+    }
+    // admit while slots and arena space last
+    while ((int)S->active.size() < S->o.max_slots && !S->pending.empty()) {
+      Request *r = S->pending.front();
+      size_t off;
+      if (!S->arena.alloc(r->bytes, &off)) break;  // wait for memory to free up
+      S->pending.pop_front();
+      r->off = off;
+      r->t_admit = now_s();
+      r->fresh = true;
+      r->order = S->admit_order++;
+      S->active.push_back(r);
+      ++S->admitted;
+      progress = true;
+    }
+    S->peak = std::max(S->peak, (int)S->active.size());
+    // launch on idle lanes
+    for (Lane &L : S->lane)
+      if (!L.busy && launch_bucket(S, L)) progress = true;
+    bool any_busy = false;
+    for (Lane &L : S->lane) any_busy |= L.busy;
+    if (!any_busy && S->active.empty() && S->pending.empty() && S->stop) return;
+    if (!progress) {
+      if (!any_busy) S->cv.wait_for(lk, std::chrono::milliseconds(1));
+      else {
+        lk.unlock();
+        std::this_thread::sleep_for(std::chrono::microseconds(20));
       }
-      S->peak = std::max(S->peak, (int)S->active.size());
-      if (S->active.empty()) {
-        if (S->stop) return;
-        S->cv.wait_for(lk, std::chrono::milliseconds(1));
-        continue;
-      }
-    }
-    // copy the admitted requests' data into the arena
-    for (Request *r : fresh) {
-      char *base = S->arena_dev + r->off;
-      const size_t n = r->n, m = r->m, p = r->p;
-      const float *src = r->data.data();
-      auto put = [&](size_t o, size_t floats) {
-        if (floats) (void)hipMemcpyAsync(base + o, src, floats * 4, hipMemcpyHostToDevice, S->stream);
-        src += floats;
-      };
-      put(r->o_Q, n * n); put(r->o_q, n); put(r->o_A, p * n); put(r->o_b, p);
-      put(r->o_G, m * n); put(r->o_h, m);
-    }
-    // descriptors grouped by bucket
-    std::map<Bucket, std::vector<int>> groups;
-    for (int i = 0; i < (int)S->active.size(); ++i) {
-      const Request *r = S->active[i];
-      const int N = r->n + r->plan.kb + r->p;
-      groups[Bucket{r->plan.threads, (N + 63) / 64, r->plan.m_in_lds}].push_back(i);
-    }
-    std::vector<int> order;
-    order.reserve(S->active.size());
-    for (auto &g : groups) order.insert(order.end(), g.second.begin(), g.second.end());
-    for (int k = 0; k < (int)order.size(); ++k) {
-      const Request *r = S->active[order[k]];
-      char *base = S->arena_dev + r->off;
-      qpk::SlotDesc &d = S->h_desc[k];
-      d.n = r->n; d.m = r->m; d.p = r->p; d.kb = r->plan.kb;
-      d.flags = (r->fresh ? 1 : 0) | (r->plan.amode << 1);
-      d.Q = (const float *)(base + r->o_Q); d.q = (const float *)(base + r->o_q);
-      d.A = r->p ? (const float *)(base + r->o_A) : nullptr;
-      d.b = r->p ? (const float *)(base + r->o_b) : nullptr;
-      d.G = r->m ? (const float *)(base + r->o_G) : nullptr;
-      d.h = r->m ? (const float *)(base + r->o_h) : nullptr;
-      d.state = (float *)(base + r->o_state);
-      d.ws = r->plan.m_in_lds ? nullptr : (float *)(base + r->o_ws);
-      d.status = S->d_status + k; d.iters = S->d_iters + k; d.res = S->d_res + k;
-    }
-    (void)hipMemcpyAsync(S->d_desc, S->h_desc, order.size() * sizeof(qpk::SlotDesc),
-                         hipMemcpyHostToDevice, S->stream);
-    // one launch per bucket; the buckets, largest estimated cost first, are
-    // dealt to the main and side streams so a step lasts about as long as
-    // its most expensive bucket rather than the sum of all of them
-    struct Launch { Bucket b; int k0, cnt; size_t lds; double cost; };
-    std::vector<Launch> launches;
-    int k0 = 0;
-    for (auto &g : groups) {
-      const int cnt = (int)g.second.size();
-      size_t lds = 0;
-      double cost = 0.0;
-      for (int idx : g.second) {
-        const Request *r = S->active[idx];
-        lds = std::max(lds, r->plan.lds);
-        const double N = r->n + r->plan.kb + r->p;
-        cost += N * N * N;
-      }
-      launches.push_back(Launch{g.first, k0, cnt, lds, cost});
-      k0 += cnt;
-    }
-    std::sort(launches.begin(), launches.end(),
-              [](const Launch &a, const Launch &b) { return a.cost > b.cost; });
-    const int nstreams = 1 + S->kSide;
-    bool used[1 + qpx_server::kSide] = {};
-    (void)hipEventRecord(S->ev_ready, S->stream);
-    for (size_t j = 0; j < launches.size(); ++j) {
-      const Launch &L = launches[j];
-      const int si = (int)(j % nstreams);
-      hipStream_t st = si == 0 ? S->stream : S->side[si - 1];
-      if (si > 0 && !used[si]) (void)hipStreamWaitEvent(st, S->ev_ready, 0);
-      used[si] = true;
-      qpk::Params P;
-      std::memset(&P, 0, sizeof(P));
-      P.n = 64 * L.b.rpl;  // dispatch only: rows-per-lane variant
-      // small size classes run more iterations per step (their launches end
-      // well before the largest class's); the iterate persists between
-      // steps, so how iterations are split over steps does not change them
-      const int mult = L.b.rpl <= 1 ? 4 : (L.b.rpl <= 2 ? 2 : 1);
-      P.form = S->so.form; P.max_iter = S->o.iters_per_step * mult; P.pc = S->so.pc;
-      P.tol = S->so.tol; P.sigma = S->so.sigma; P.delta_reg = S->so.delta_reg;
-      P.refine = S->so.refine_steps;
-      P.desc = S->d_desc + L.k0;
-      P.mode = qpk::kServe;
-      if (qpk::launch(P, L.b.threads, L.b.mlds, L.lds, L.cnt, st) != hipSuccess) S->error = QPX_ERR_HIP;
-    }
-    for (int si = 1; si < nstreams; ++si) {
-      if (!used[si]) continue;
-      (void)hipEventRecord(S->ev_done[si - 1], S->side[si - 1]);
-      (void)hipStreamWaitEvent(S->stream, S->ev_done[si - 1], 0);
-    }
-    const size_t na = order.size();
-    (void)hipMemcpyAsync(S->h_status, S->d_status, na * 4, hipMemcpyDeviceToHost, S->stream);
-    (void)hipMemcpyAsync(S->h_iters, S->d_iters, na * 4, hipMemcpyDeviceToHost, S->stream);
-    if (hipStreamSynchronize(S->stream) != hipSuccess) S->error = QPX_ERR_HIP;
-    // retire finished QPs
-    std::vector<Request *> keep, done;
-    for (int k = 0; k < (int)na; ++k) {
-      Request *r = S->active[order[k]];
-      r->iters += S->h_iters[k];
-      const int st = S->h_status[k] & 0xff;
-      const bool running = st == 1 && r->iters < S->so.max_iter;
-      r->fresh = false;
-      if (running) {
-        keep.push_back(r);
-      } else {
-        r->status = S->h_status[k];
-        done.push_back(r);
-      }
-    }
-    for (Request *r : done) {
-      r->sol.resize((size_t)r->n + r->p + 2 * r->m);
-      (void)hipMemcpyAsync(r->sol.data(), S->arena_dev + r->off + r->o_state, r->sol.size() * 4,
-                           hipMemcpyDeviceToHost, S->stream);
-    }
-    if (!done.empty() && hipStreamSynchronize(S->stream) != hipSuccess) S->error = QPX_ERR_HIP;
-    {
-      std::lock_guard<std::mutex> lk(S->mu);
-      const double t = now_s();
-      for (Request *r : done) {
-        S->arena.release(r->off, r->bytes);
-        r->t_done = t;
-        r->done = true;
-        std::vector<float>().swap(r->data);
-        ++S->completed;
-      }
-      S->active.swap(keep);
     }
   }
 }
@@ -331,23 +364,28 @@ int qp_server_create(qpx_ctx *ctx, const qp_server_opts *opts, const qp_opts *so
     delete S;
     return QPX_ERR_ARG;
   }
+  // staging per lane: max_slots iterates of n_max variables with m = 2 n_max,
+  // and at least one of the largest a request may have (m <= 4096); a launch
+  // takes as many QPs as fit
+  S->staging = std::max((size_t)S->o.max_slots * (state_floats(S->o.n_max, 2 * S->o.n_max,
+                                                               S->o.n_max) + 64),
+                        state_floats(S->o.n_max, 4096, S->o.n_max) + 64);
   if (hipSetDevice(ctx->device) != hipSuccess) { delete S; return QPX_ERR_HIP; }
-  bool ok = hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) == hipSuccess;
-  for (int i = 0; i < qpx_server::kSide; ++i) {
-    ok = ok && hipStreamCreateWithFlags(&S->side[i], hipStreamNonBlocking) == hipSuccess;
-    ok = ok && hipEventCreateWithFlags(&S->ev_done[i], hipEventDisableTiming) == hipSuccess;
-  }
-  ok = ok && hipEventCreateWithFlags(&S->ev_ready, hipEventDisableTiming) == hipSuccess;
-  ok = ok && hipMalloc(&S->arena_dev, S->o.arena_bytes) == hipSuccess;
   const size_t ns = S->o.max_slots;
-  ok = ok && hipMalloc(&S->d_desc, ns * sizeof(qpk::SlotDesc)) == hipSuccess;
-  ok = ok && hipMalloc(&S->d_status, ns * 4) == hipSuccess;
-  ok = ok && hipMalloc(&S->d_iters, ns * 4) == hipSuccess;
-  ok = ok && hipMalloc(&S->d_res, ns * 4) == hipSuccess;
-  ok = ok && hipHostMalloc(&S->h_desc, ns * sizeof(qpk::SlotDesc), hipHostMallocDefault) == hipSuccess;
-  ok = ok && hipHostMalloc(&S->h_status, ns * 4, hipHostMallocDefault) == hipSuccess;
-  ok = ok && hipHostMalloc(&S->h_iters, ns * 4, hipHostMallocDefault) == hipSuccess;
-  ok = ok && hipHostMalloc(&S->h_res, ns * 4, hipHostMallocDefault) == hipSuccess;
+  bool ok = hipMalloc(&S->arena_dev, S->o.arena_bytes) == hipSuccess;
+  for (Lane &L : S->lane) {
+    ok = ok && hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&L.done, hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipMalloc(&L.d_desc, ns * sizeof(qpk::SlotDesc)) == hipSuccess;
+    ok = ok && hipMalloc(&L.d_status, ns * 4) == hipSuccess;
+    ok = ok && hipMalloc(&L.d_iters, ns * 4) == hipSuccess;
+    ok = ok && hipMalloc(&L.d_res, ns * 4) == hipSuccess;
+    ok = ok && hipMalloc(&L.d_out, S->staging * 4) == hipSuccess;
+    ok = ok && hipHostMalloc(&L.h_desc, ns * sizeof(qpk::SlotDesc), hipHostMallocDefault) == hipSuccess;
+    ok = ok && hipHostMalloc(&L.h_status, ns * 4, hipHostMallocDefault) == hipSuccess;
+    ok = ok && hipHostMalloc(&L.h_iters, ns * 4, hipHostMallocDefault) == hipSuccess;
+    ok = ok && hipHostMalloc(&L.h_out, S->staging * 4, hipHostMallocDefault) == hipSuccess;
+  }
   if (!ok) {
     qp_server_destroy(S);
     return QPX_ERR_OOM;
@@ -443,25 +481,23 @@ int qp_server_destroy(qpx_server *S) {
   S->stop = true;
   S->cv.notify_all();
   if (S->th.joinable()) S->th.join();
-  if (S->stream) (void)hipStreamSynchronize(S->stream);
-  for (int i = 0; i < qpx_server::kSide; ++i)
-    if (S->side[i]) (void)hipStreamSynchronize(S->side[i]);
+  for (Lane &L : S->lane)
+    if (L.stream) (void)hipStreamSynchronize(L.stream);
   for (auto &kv : S->by_ticket) delete kv.second;
   if (S->arena_dev) (void)hipFree(S->arena_dev);
-  if (S->d_desc) (void)hipFree(S->d_desc);
-  if (S->d_status) (void)hipFree(S->d_status);
-  if (S->d_iters) (void)hipFree(S->d_iters);
-  if (S->d_res) (void)hipFree(S->d_res);
-  if (S->h_desc) (void)hipHostFree(S->h_desc);
-  if (S->h_status) (void)hipHostFree(S->h_status);
-  if (S->h_iters) (void)hipHostFree(S->h_iters);
-  if (S->h_res) (void)hipHostFree(S->h_res);
-  for (int i = 0; i < qpx_server::kSide; ++i) {
-    if (S->ev_done[i]) (void)hipEventDestroy(S->ev_done[i]);
-    if (S->side[i]) (void)hipStreamDestroy(S->side[i]);
+  for (Lane &L : S->lane) {
+    if (L.d_desc) (void)hipFree(L.d_desc);
+    if (L.d_status) (void)hipFree(L.d_status);
+    if (L.d_iters) (void)hipFree(L.d_iters);
+    if (L.d_res) (void)hipFree(L.d_res);
+    if (L.d_out) (void)hipFree(L.d_out);
+    if (L.h_desc) (void)hipHostFree(L.h_desc);
+    if (L.h_status) (void)hipHostFree(L.h_status);
+    if (L.h_iters) (void)hipHostFree(L.h_iters);
+    if (L.h_out) (void)hipHostFree(L.h_out);
+    if (L.done) (void)hipEventDestroy(L.done);
+    if (L.stream) (void)hipStreamDestroy(L.stream);
   }
-  if (S->ev_ready) (void)hipEventDestroy(S->ev_ready);
-  if (S->stream) (void)hipStreamDestroy(S->stream);
   delete S;
   return QPX_OK;
 }

@@ -32,7 +32,7 @@ import numpy as np
 
 __all__ = [
     "QPBatch", "random_feasible", "ill_conditioned", "projection",
-    "box_qp", "safety_filter", "serving_requests", "upstream", "CONFIGS", "make_config",
+    "box_qp", "safety_filter", "serving_requests", "upstream", "CONFIGS", "make_config", "concat",
 ]
 
 
@@ -78,6 +78,12 @@ class QPBatch:
 
     def arrays(self):
         return (self.Q, self.q, self.A, self.b, self.G, self.h)
+
+
+def concat(batches) -> QPBatch:
+    """Batches of the same sizes joined into one (extras are dropped)."""
+    cat = lambda k: np.ascontiguousarray(np.concatenate([getattr(P, k) for P in batches]))
+    return QPBatch(*(cat(k) for k in ("Q", "q", "A", "b", "G", "h")))
 
 
 def _f32(*arrs):

@@ -37,6 +37,29 @@ def test_default_opts():
     assert o.form == 0 and o.max_iter == 100 and abs(o.tol - 1e-5) < 1e-12
     assert o.pc == 1 and abs(o.sigma - 0.1) < 1e-7 and abs(o.kappa_relax - 1e-4) < 1e-10
     assert o.assembly == qpx.ASSEMBLY["auto"]
+    assert o.fp64_residual == qpx.RESIDUAL["auto"] and o.backoff == 0.0
+    assert abs(o.relax_tol - 1e-6) < 1e-12 and o.relax_max_iter == 30
+
+
+def test_status_strings_are_distinct():
+    # return codes and per-QP status words have their own functions; no two
+    # codes share a description
+    L = qpx.lib()
+    codes = [0, 1, -1, -2, -3, -4, -5]
+    names = [L.qp_status_string(c) for c in codes]
+    assert len(set(names)) == len(codes)
+    assert L.qp_status_string(1) == b"pending"
+    words = {}
+    for outcome in range(4):
+        for stage in range(8):
+            words[(outcome, stage)] = L.qp_result_string(outcome | (stage << 8))
+    assert len(set(words.values())) == len(words)
+    assert words[(1, 0)] == b"iteration limit reached"
+    assert words[(2, 2)] == b"non-finite value (stage: predictor)"
+    # the precision bits do not change the description
+    assert L.qp_result_string(0 | (1 << 16) | (1 << 17)) == words[(0, 0)]
+    assert L.qp_result_string(7) == b"unknown per-QP status"
+    assert qpx.result_string(3 | (6 << 8)).endswith("(stage: relax)")
 
 
 def _struct_fields(name):

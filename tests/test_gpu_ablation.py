@@ -40,13 +40,18 @@ def _run(insts, form, kr, tol):
 def test_bounded_form_matches_oracle_on_projection():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
+    import parity as pt
     insts = _instances()
     st, rst, grad = _run(insts, "bounded", 1e-4, 1e-5)
-    assert np.all((st & 0xff) == 0) and np.all((rst & 0xff) <= 1)
+    assert np.all((st & 0xff) == 0) and np.all((rst & 0xff) == 0)
     for k, (P, v) in enumerate(insts):
         ref, _ = gradients.grad_at_relaxed(*P.one(0), 1e-4, v.astype(np.float64))
-        err = np.linalg.norm(grad[k] + ref["q"]) / max(1e-3, np.linalg.norm(ref["q"]))
-        assert err <= 1e-3, (k, err)
+        # the gradient with respect to the query point is -dl/dq; its
+        # natural scale is |v| (the projection's Jacobian has norm <= 1), so
+        # near a vertex, where it vanishes, the bound does not shrink below
+        # 1e-3 of |v|
+        pt.assert_close(f"projection {k} dx/dquery", grad[k], -ref["q"],
+                        pt.GRAD_TOL * max(pt.inf(ref["q"]), 1e-3 * pt.inf(v)), pt.GRAD_TOL)
 
 
 def test_bounded_gradient_tracks_the_relaxation_floor():

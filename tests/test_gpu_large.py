@@ -1,61 +1,52 @@
-"""GPU parity on the large-size paths, against the FP64 oracle.
+"""GPU parity on the large-size paths, against the FP64 oracle (entry by
+entry, tolerances in tests/parity.py).
 
 * The bordered factor in global memory: with n = 128, m = 256, p = 16 the
-  factor (N up to 272 rows) needs about 161 KB, more than a workgroup's LDS,
-  and the solves run with 8 rows per lane; with n = 256, m = 512, p = 32 the
-  system has up to 544 rows and the solves run with 16 rows per lane.
+  factor (N up to 400 rows) needs more than a workgroup's LDS and the solves
+  run with 8 rows per lane; with n = 256, m = 512, p = 32 the system has up
+  to 800 rows and the solves run with 16 rows per lane.
 * Each H-block assembly arithmetic (FP32 vector ALUs, BF16x3 split products
   on the matrix cores with refinement, FP32 on the matrix cores).
-* The ill-conditioned, degenerate shape (Q with eigenvalues down to 1e-4,
-  half of the 512 rows active, plus 32 equalities, in R^256): x is unique,
-  the multipliers are not, so x is compared with the oracle's and with the
-  planted optimum.
-
-Tolerances as in test_gpu_parity: x within 1e-4 (relative, 2-norm) of the
-oracle, and duals within 1e-3 where the duals are unique; for the
-ill-conditioned shape also x within 1e-4 of the planted optimum.
+* The ill-conditioned, degenerate workload (512 QPs, Q with eigenvalues
+  log-uniform in [1e-4, 1], half of the 512 rows active plus 32 equalities in
+  R^256): x is unique, the multipliers are not, so x is compared with the
+  oracle's and with the planted optimum.  This workload is solved to 1e-6:
+  the scaled residual does not bound the error in x well enough on it (at
+  1e-5, 2 of the 512 QPs end 1.2-1.6e-4 from the planted optimum).  Its
+  gradients are taken at kappa_relax = 1e-3 (the paper's float32 setting for
+  its hardest workload): at 1e-4 the Schur complement of the bordered
+  system has a condition number of about 2e8 (measured with the oracle at
+  the relaxed point), beyond what a float32 factorisation resolves.
 """
 import numpy as np
 import pytest
 
 import qpgen
-from oracle import implicit
+from oracle import implicit, gradients
+
+import parity as pt
 
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
-
-def _dev():
-    if not torch.cuda.is_available():
-        pytest.skip("no GPU")
-    return torch.device("cuda:0")
+C5_TOL = 1e-6
+C5_KAPPA_RELAX = 1e-3
 
 
 def _run(P, **kw):
     import paper_2605_17913_amd as qpx
-    d = _dev()
-    Q, q, A, b, G, h = [torch.from_numpy(a).to(d) for a in P.arrays()]
-    sol = qpx.solve(Q, q, A, b, G, h, **kw)
+    sol = qpx.solve(*pt.to_dev(P), **kw)
     torch.cuda.synchronize()
-    return {k: v.cpu().numpy() for k, v in sol.items()}
+    return pt.npd(sol)
 
 
-def _rel(a, b):
-    return float(np.linalg.norm(a - b) / max(1.0, np.linalg.norm(b)))
-
-
-def _parity(P, sol, idx, xtol, dtol):
+def _parity(what, P, sol, idx, duals=True):
     worst = 0.0
     for i in idx:
         r = implicit.solve_qp(*P.one(i), tol=1e-11, max_iter=200)
         assert r.status == implicit.CONVERGED
-        ex = _rel(sol["x"][i], r.x)
-        worst = max(worst, ex)
-        assert ex <= xtol, (i, ex)
-        if dtol is not None:
-            ez = float(np.max(np.abs(sol["z"][i] - r.z)) / max(1.0, np.max(np.abs(r.z))))
-            assert ez <= dtol, (i, ez)
+        worst = max(worst, pt.check_point(f"{what} QP {i}", P, i, sol, r, duals=duals))
     return worst
 
 
@@ -64,88 +55,79 @@ def test_global_factor_path_n128(assembly):
     P = qpgen.random_feasible(8, 128, 256, 16, seed=9)
     print(f"global factor n=128 m=256 p=16 B=8 assembly={assembly}", flush=True)
     sol = _run(P, assembly=assembly)
-    st = sol["status"] & 0xFF
+    st = pt.outcome(sol["status"])
     assert np.all(st == 0), (st.tolist(), sol["iters"].tolist())
-    worst = _parity(P, sol, [0, 3, 7], 1e-4, 1e-3)
-    print(f"  iters {sol['iters'].tolist()} worst x err {worst:.2e}", flush=True)
+    worst = _parity("n=128", P, sol, [0, 3, 7])
+    print(f"  iters {sol['iters'].tolist()} worst entry at {worst:.2f} of its bound", flush=True)
 
 
 def test_sixteen_rows_per_lane_n256():
     P = qpgen.random_feasible(4, 256, 512, 32, seed=10)
-    print("global factor n=256 m=512 p=32 B=4 (up to 544 rows)", flush=True)
+    print("global factor n=256 m=512 p=32 B=4 (up to 800 rows)", flush=True)
     sol = _run(P)
-    st = sol["status"] & 0xFF
+    st = pt.outcome(sol["status"])
     assert np.all(st == 0), (st.tolist(), sol["iters"].tolist())
-    worst = _parity(P, sol, [0, 2], 1e-4, 1e-3)
-    print(f"  iters {sol['iters'].tolist()} worst x err {worst:.2e}", flush=True)
+    worst = _parity("n=256", P, sol, [0, 2])
+    print(f"  iters {sol['iters'].tolist()} worst entry at {worst:.2f} of its bound", flush=True)
 
 
-def test_ill_conditioned_degenerate():
+def test_ill_conditioned_degenerate_vs_oracle():
     P = qpgen.ill_conditioned(4, 256, 512, 32, seed=0)
     print("ill-conditioned degenerate n=256 m=512 p=32 B=4", flush=True)
-    sol = _run(P)
-    st = sol["status"] & 0xFF
-    errs = [_rel(sol["x"][i], P.extra["x_star"][i]) for i in range(P.B)]
-    print(f"  status {st.tolist()} iters {sol['iters'].tolist()} "
-          f"x err vs planted {[f'{e:.1e}' for e in errs]}", flush=True)
-    assert np.all(st == 0), st.tolist()
-    assert max(errs) <= 1e-4, errs
-    _parity(P, sol, [0], 1e-4, None)
+    sol = _run(P, tol=C5_TOL)
+    assert np.all(pt.outcome(sol["status"]) == 0), sol["status"].tolist()
+    for i in range(P.B):
+        pt.check_x(f"planted QP {i}", sol["x"][i], P.extra["x_star"][i])
+    _parity("ill-conditioned", P, sol, [0, 3], duals=False)
 
 
-def test_ill_conditioned_batch_all_converge():
-    # the benchmark's 512-QP batch of the ill-conditioned shape: every QP
-    # converges and matches the planted optimum (which the FP64 oracle
-    # reproduces to 1e-7).  The scaled residual does not bound the error in
-    # x on this shape (smallest eigenvalue of Q 1e-4): at tol 1e-5, 2 of the
-    # 512 QPs are 1.6e-4 away; at 1e-6 (0.6 more iterations on average)
-    # every QP is within 2e-5, so the test asks for 1e-6.
-    P = qpgen.ill_conditioned(512, 256, 512, 32, seed=4)
-    print("ill-conditioned degenerate n=256 m=512 p=32 B=512 tol=1e-6 (default assembly)",
-          flush=True)
-    sol = _run(P, tol=1e-6)
-    st = sol["status"] & 0xFF
-    errs = np.array([_rel(sol["x"][i], P.extra["x_star"][i]) for i in range(P.B)])
-    print(f"  failed {np.nonzero(st)[0].tolist()} worst x err {errs.max():.2e}", flush=True)
+@pytest.mark.parametrize("assembly", ["auto", "bf16x3"])
+def test_ill_conditioned_batch_all_converge(assembly):
+    # the benchmark's 512-QP batch of the ill-conditioned workload at the
+    # benchmark's settings: every QP converges and matches the planted
+    # optimum entry by entry (the FP64 oracle reproduces it to 1e-7).  With
+    # BF16x3 split-product assembly, a QP whose refinement stops contracting
+    # switches to FP32 matrix-core assembly (status bit 17), so every QP
+    # still meets the tolerance.
+    P = qpgen.make_config("illcond", seed=4)
+    print(f"ill-conditioned degenerate B=512 tol={C5_TOL} assembly={assembly}", flush=True)
+    sol = _run(P, tol=C5_TOL, assembly=assembly)
+    st = pt.outcome(sol["status"])
     assert np.all(st == 0), np.nonzero(st)[0].tolist()
-    assert errs.max() <= 1e-4, (int(errs.argmax()), float(errs.max()))
+    worst = 0.0
+    for i in range(P.B):
+        worst = max(worst, pt.check_x(f"planted QP {i}", sol["x"][i], P.extra["x_star"][i]))
+    fell = int(np.sum((sol["status"] >> 17) & 1))
+    f64 = int(np.sum((sol["status"] >> 16) & 1))
+    print(f"  worst entry at {worst:.2f} of its bound; FP64 refinement residuals on {f64} QPs, "
+          f"BF16x3 fallback on {fell}", flush=True)
 
 
 def test_ill_conditioned_gradients():
-    # IFT gradients on the degenerate shape against the FP64 oracle at
-    # kappa_relax = 1e-3 (the paper's FP32 setting for its hardest workload).
-    # At 1e-4 the relaxation does not reach its tolerance within 30
-    # iterations on this shape (status MAX_ITER) and the gradient is not
-    # accurate; the status tells the caller.
     import paper_2605_17913_amd as qpx
-    from oracle import gradients
-    d = _dev()
-    P = qpgen.ill_conditioned(2, 256, 512, 32, seed=1)
-    print("ill-conditioned gradients n=256 m=512 p=32 B=2 kappa_relax=1e-3", flush=True)
-    Q, q, A, b, G, h = [torch.from_numpy(a).to(d) for a in P.arrays()]
-    sol = qpx.solve(Q, q, A, b, G, h, tol=1e-6)
+    P = qpgen.ill_conditioned(4, 256, 512, 32, seed=1)
+    print(f"ill-conditioned gradients B=4 kappa_relax={C5_KAPPA_RELAX}", flush=True)
+    T = pt.to_dev(P)
+    sol = qpx.solve(*T, tol=C5_TOL)
     gx = qpgen.upstream(P.B, 256, seed=2)
-    g = qpx.backward(Q, q, A, b, G, h, sol, torch.from_numpy(gx).to(d), kappa_relax=1e-3,
-                     relaxed=True)
-    torch.cuda.synchronize()
-    # converged, or stopped at relax_max_iter just short of relax_tol (the
-    # default refinement leaves the relaxed residual near 1e-7 on this shape;
-    # refine_steps=8 converges it): the gradients are checked either way
-    assert int(g["relaxed"]["status"][0].item()) & 0xFF <= 1
-    ref, rr = gradients.grad_at_relaxed(*P.one(0), 1e-3, gx[0].astype(np.float64))
-    assert _rel(g["relaxed"]["x"][0].cpu().numpy(), rr.x) <= 1e-4
-    for key in ("Q", "q", "A", "b", "G", "h"):
-        gg = g[key][0].cpu().numpy()
-        err = np.linalg.norm(gg - ref[key]) / max(1e-3, np.linalg.norm(ref[key]))
-        print(f"  d{key} err {err:.2e}", flush=True)
-        assert err <= 1e-3, (key, err)
+    g = pt.npd(qpx.backward(*T, sol, torch.from_numpy(gx).to(T[0].device),
+                            kappa_relax=C5_KAPPA_RELAX, relaxed=True))
+    rst = pt.outcome(g["relaxed"]["status"])
+    assert np.all(rst == 0), (rst.tolist(), g["relaxed"]["iters"].tolist())
+    worst = 0.0
+    for i in range(P.B):
+        ref, rr = gradients.grad_at_relaxed(*P.one(i), C5_KAPPA_RELAX,
+                                            gx[i].astype(np.float64))
+        pt.check_x(f"relaxed QP {i}", g["relaxed"]["x"][i], rr.x)
+        worst = max(worst, pt.check_grads(f"ill-conditioned QP {i}", g, i, ref))
+    print(f"  worst gradient entry at {worst:.2f} of its bound", flush=True)
 
 
 def test_workspace_shared_across_streams():
     # the context's global factor workspace is shared; solves enqueued on two
     # streams one after the other must not overlap on it
     import paper_2605_17913_amd as qpx
-    d = _dev()
+    d = pt.dev()
     P1 = qpgen.random_feasible(64, 128, 256, 16, seed=21)
     P2 = qpgen.random_feasible(64, 128, 256, 16, seed=22)
     T1 = [torch.from_numpy(a).to(d) for a in P1.arrays()]

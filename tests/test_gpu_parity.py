@@ -1,141 +1,101 @@
-"""GPU parity: the HIP path (through the C-ABI) against the FP64 oracle.
+"""GPU parity: the HIP path (through the C-ABI) against the FP64 oracle,
+entry by entry (tolerances in tests/parity.py).
 
-Tolerances (float32 path vs float64 oracle on identical float32 inputs):
-  x        ||x - x*||_2 / max(1, ||x*||_2) <= 1e-4
-  y, z     ||d - d*||_inf / max(1, ||d*||_inf) <= 1e-3 (duals are unique here)
-  grads    ||g - g*||_2 / max(1e-3, ||g*||_2) <= 1e-3 per parameter block
-The stopping tolerance is 1e-5 on the scaled residuals (the reading of the
-paper's ||r||_inf < tol that float32 can reach).
+The solve stops at 1e-5 on the scaled KKT residuals (the reading of the
+paper's ||r||_inf < tol that float32 can reach); every QP of a checked batch
+must converge, and the checked QPs are compared in x, s, y and z.
 """
 import numpy as np
 import pytest
 
 import qpgen
-from oracle import implicit, standard, gradients
+from oracle import implicit, gradients
+
+import parity as pt
 
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
 
-def _dev():
-    if not torch.cuda.is_available():
-        pytest.skip("no GPU")
-    return torch.device("cuda:0")
-
-
-def _to_dev(P):
-    d = _dev()
-    return [torch.from_numpy(a).to(d) for a in P.arrays()]
-
-
-def _rel(a, b):
-    return float(np.linalg.norm(a - b) / max(1.0, np.linalg.norm(b)))
-
-
-def _oracle_solutions(P, idx, tol=1e-11):
-    out = []
-    for i in idx:
-        r = implicit.solve_qp(*P.one(i), tol=tol, max_iter=200)
-        assert r.status == implicit.CONVERGED
-        out.append(r)
-    return out
+def _oracle(P, i, tol=1e-11):
+    r = implicit.solve_qp(*P.one(i), tol=tol, max_iter=200)
+    assert r.status == implicit.CONVERGED
+    return r
 
 
 def _run(P, **kw):
     import paper_2605_17913_amd as qpx
-    Q, q, A, b, G, h = _to_dev(P)
-    sol = qpx.solve(Q, q, A, b, G, h, **kw)
+    sol = qpx.solve(*pt.to_dev(P), **kw)
     torch.cuda.synchronize()
-    return {k: v.cpu().numpy() for k, v in sol.items()}
+    return pt.npd(sol)
 
 
-def _check_solution(P, sol, idx, xtol=1e-4, dtol=1e-3):
-    ref = _oracle_solutions(P, idx)
+def _check_batch(what, P, sol, idx, tol=1e-5):
+    st = pt.outcome(sol["status"])
+    assert np.all(st == 0), (what, np.nonzero(st)[0].tolist())
     worst = 0.0
-    for k, i in enumerate(idx):
-        r = ref[k]
-        ex = _rel(sol["x"][i], r.x)
-        worst = max(worst, ex)
-        assert ex <= xtol, (i, ex)
-        if P.m:
-            ez = np.max(np.abs(sol["z"][i] - r.z)) / max(1.0, np.max(np.abs(r.z)))
-            assert ez <= dtol, (i, ez)
-        if P.p:
-            ey = np.max(np.abs(sol["y"][i] - r.y)) / max(1.0, np.max(np.abs(r.y)))
-            assert ey <= dtol, (i, ey)
+    for i in idx:
+        worst = max(worst, pt.check_point(f"{what} QP {i}", P, i, sol, _oracle(P, i), tol))
+    print(f"{what}: worst entry at {worst:.2f} of its bound", flush=True)
     return worst
 
 
 @pytest.mark.parametrize("pc", [True, False])
 def test_plain_config_bounded(pc):
     P = qpgen.make_config("plain", seed=0)
+    print(f"plain config B=64 n=10 m=20 p=2 pc={pc}", flush=True)
     sol = _run(P, pc=pc)
-    assert np.all(sol["status"] == 0), sol["status"]
-    _check_solution(P, sol, range(P.B))
+    _check_batch("plain", P, sol, range(P.B))
 
 
 def test_plain_config_tail_and_ragged_sizes():
     # sizes that are not multiples of the tile / panel widths
-    for (n, m, p, seed) in [(7, 13, 1, 1), (17, 35, 3, 2), (33, 70, 5, 3), (3, 1, 0, 4)]:
+    for (n, m, p, seed) in [(7, 13, 1, 1), (17, 35, 3, 2), (33, 70, 5, 3), (3, 1, 0, 4),
+                            (65, 130, 7, 5)]:
         P = qpgen.random_feasible(9, n, m, p, seed)
-        sol = _run(P)
-        assert np.all(sol["status"] == 0), (n, m, p, sol["status"])
-        _check_solution(P, sol, range(P.B))
+        print(f"ragged n={n} m={m} p={p}", flush=True)
+        _check_batch(f"ragged n={n}", P, _run(P), range(P.B))
 
 
 def test_box_qp_closed_form():
     P = qpgen.box_qp(32, 12, seed=3)
     sol = _run(P)
-    assert np.all(sol["status"] == 0)
+    assert np.all(pt.outcome(sol["status"]) == 0)
     for i in range(P.B):
         xs = np.clip(-P.q[i] / P.extra["d"][i], P.extra["lo"][i], P.extra["hi"][i])
-        assert np.max(np.abs(sol["x"][i] - xs)) < 1e-4
+        pt.check_x(f"box QP {i}", sol["x"][i], xs)
 
 
 def test_unconstrained_and_equality_only():
+    # without inequalities the initial KKT solve (refined) is the answer
     P = qpgen.random_feasible(8, 12, 0, 0, seed=5)
     sol = _run(P)
-    assert np.all(sol["status"] == 0)
+    assert np.all(pt.outcome(sol["status"]) == 0), sol["status"]
     for i in range(P.B):
         Q, q, A, b, G, h = P.one(i)
-        assert _rel(sol["x"][i], -np.linalg.solve(Q, q)) < 1e-4
+        pt.check_x(f"unconstrained QP {i}", sol["x"][i], -np.linalg.solve(Q, q))
     P = qpgen.random_feasible(8, 12, 0, 4, seed=6)
-    sol = _run(P)
-    assert np.all(sol["status"] == 0)
-    _check_solution(P, sol, range(P.B))
-
-
-def test_standard_arm_on_plain_config():
-    # the explicit arm runs on the same inputs; in FP32 it may fail on some
-    # QPs (the paper's point) but every converged QP must be right
-    P = qpgen.make_config("plain", seed=0)
-    sol = _run(P, form="standard")
-    ok = np.where(sol["status"] == 0)[0]
-    assert len(ok) > 0
-    ref = _oracle_solutions(P, ok)
-    for k, i in enumerate(ok):
-        assert _rel(sol["x"][i], ref[k].x) <= 1e-3
+    _check_batch("equality-only", P, _run(P), range(P.B))
 
 
 def test_throughput_config_sampled():
     P = qpgen.make_config("throughput", seed=0)
+    print("throughput config B=4096 n=50 m=100 p=10 (16 QPs sampled)", flush=True)
     sol = _run(P)
-    bad = np.where(sol["status"] != 0)[0]
-    assert len(bad) == 0, [(int(i), int(sol["status"][i]), int(sol["iters"][i])) for i in bad[:8]]
-    idx = np.random.default_rng(0).choice(P.B, 12, replace=False)
-    _check_solution(P, sol, idx)
+    idx = np.random.default_rng(0).choice(P.B, 16, replace=False)
+    _check_batch("throughput", P, sol, idx)
 
 
 def test_deterministic_and_batch_order_invariant():
     P = qpgen.random_feasible(40, 20, 40, 4, seed=7)
     a = _run(P)
     b = _run(P)
-    for k in ("x", "y", "z", "s", "iters"):
+    for k in ("x", "y", "z", "s", "iters", "status"):
         assert np.array_equal(a[k], b[k]), k
     perm = np.random.default_rng(1).permutation(P.B)
     c = _run(P.subset(perm))
-    for k in ("x", "z", "iters"):
+    for k in ("x", "y", "z", "s", "iters"):
         assert np.array_equal(a[k][perm], c[k]), k
 
 
@@ -146,46 +106,94 @@ def test_deterministic_global_factor_path():
     b = _run(P)
     for k in ("x", "z", "iters", "status"):
         assert np.array_equal(a[k], b[k]), k
-    assert np.all(a["status"] == 0)
-    _check_solution(P, a, [0, 5, 15])
+    _check_batch("global factor n=100", P, a, [0, 5, 15])
 
 
 def test_empty_batch():
     import paper_2605_17913_amd as qpx
-    d = _dev()
+    d = pt.dev()
     Q = torch.zeros(0, 4, 4, device=d)
     sol = qpx.solve(Q, torch.zeros(0, 4, device=d), None, None,
                     torch.zeros(0, 3, 4, device=d), torch.zeros(0, 3, device=d))
     assert sol["x"].shape == (0, 4)
 
 
-def _grads_check(P, kr, gtol=1e-3, idx=None):
+def _grads_check(what, P, kr, idx=None, solve_tol=1e-5, seed=11):
+    """Solve at `solve_tol`, relax to kr and differentiate; the relaxed point
+    (x, s, y, z: unique for kappa > 0) and the six gradient blocks of the
+    QPs in idx against the FP64 oracle."""
     import paper_2605_17913_amd as qpx
-    Q, q, A, b, G, h = _to_dev(P)
-    sol = qpx.solve(Q, q, A, b, G, h, tol=1e-6)
-    gx_np = qpgen.upstream(P.B, P.n, seed=11)
-    gx = torch.from_numpy(gx_np).to(Q.device)
-    g = qpx.backward(Q, q, A, b, G, h, sol, gx, kappa_relax=kr, relaxed=True)
+    T = pt.to_dev(P)
+    sol = qpx.solve(*T, tol=solve_tol)
+    gx_np = qpgen.upstream(P.B, P.n, seed=seed)
+    g = qpx.backward(*T, sol, torch.from_numpy(gx_np).to(T[0].device), kappa_relax=kr,
+                     relaxed=True)
     torch.cuda.synchronize()
-    g = {k: (v.cpu().numpy() if not isinstance(v, dict) else {kk: vv.cpu().numpy() for kk, vv in v.items()})
-         for k, v in g.items()}
+    g = pt.npd(g)
+    assert np.all(pt.outcome(pt.npd(sol)["status"]) == 0)
+    rst = pt.outcome(g["relaxed"]["status"])
+    assert np.all(rst == 0), (what, "relaxation did not converge", np.nonzero(rst)[0].tolist())
+    worst = 0.0
     idx = range(P.B) if idx is None else idx
     for i in idx:
         ref, rr = gradients.grad_at_relaxed(*P.one(i), kr, gx_np[i].astype(np.float64))
-        assert _rel(g["relaxed"]["x"][i], rr.x) <= 1e-4
-        for key in ("Q", "q", "A", "b", "G", "h"):
-            if ref[key].size == 0:
-                continue
-            err = np.linalg.norm(g[key][i] - ref[key]) / max(1e-3, np.linalg.norm(ref[key]))
-            assert err <= gtol, (i, key, err)
+        worst = max(worst, pt.check_point(f"{what} relaxed QP {i}", P, i, g["relaxed"], rr,
+                                          tol=1e-6))
+        worst = max(worst, pt.check_grads(f"{what} QP {i}", g, i, ref))
+    print(f"{what}: worst entry at {worst:.2f} of its bound", flush=True)
 
 
 @pytest.mark.parametrize("kr", [1e-2, 1e-4])
 def test_backward_plain_config(kr):
     P = qpgen.random_feasible(16, 10, 20, 2, seed=9)
-    _grads_check(P, kr)
+    print(f"backward B=16 n=10 m=20 p=2 kappa_relax={kr}", flush=True)
+    _grads_check(f"plain kr={kr}", P, kr)
 
 
-def test_backward_differentiation_shape_sampled():
-    P = qpgen.random_feasible(64, 100, 200, 20, seed=2)
-    _grads_check(P, 1e-4, idx=[0, 17, 63])
+def test_differentiation_config_sampled():
+    # the differentiation workload (1024 QPs, n=100, m=200, p=20) at the
+    # benchmark's settings: forward to 1e-5, relax to 1e-4; every QP
+    # converges in both stages; 6 QPs are compared entry by entry
+    P = qpgen.make_config("differentiation", seed=0)
+    print("differentiation config B=1024 n=100 m=200 p=20 (6 QPs sampled)", flush=True)
+    idx = [0, 1, 255, 511, 700, 1023]
+    sol = _run(P)
+    _check_batch("differentiation forward", P, sol, idx[:3])
+    _grads_check("differentiation", P, 1e-4, idx=idx)
+
+
+def test_differentiation_finite_differences():
+    # GPU gradients against central differences of the FP64 oracle's relaxed
+    # map at the step the differentiation workload specifies (1e-3), on a
+    # stated subset: 2 QPs of the workload x 2 unit-norm random directions
+    # per parameter block (symmetric for Q).  At this shape the oracle's own
+    # differences agree with its IFT product to < 1e-4 relative at step 1e-3
+    # (tests/test_oracle_gradients.py), so the bound is the gradient
+    # tolerance on the block plus that truncation error.
+    import paper_2605_17913_amd as qpx
+    kr = 1e-4
+    P = qpgen.make_config("differentiation", seed=0, B=2)
+    T = pt.to_dev(P)
+    sol = qpx.solve(*T)
+    gx = qpgen.upstream(P.B, P.n, seed=11)
+    g = pt.npd(qpx.backward(*T, sol, torch.from_numpy(gx).to(T[0].device), kappa_relax=kr,
+                            relaxed=True))
+    assert np.all(pt.outcome(g["relaxed"]["status"]) == 0)
+    rng = np.random.default_rng(2024)
+    worst = 0.0
+    for i in range(P.B):
+        prob = P.one(i)
+        rr = gradients.relaxed_point(*prob, kr)
+        warm = (rr.x, rr.y, rr.z, rr.s)
+        for k, key in enumerate(pt.BLOCKS):
+            for _ in range(2):
+                D = rng.standard_normal(np.shape(prob[k]))
+                if key == "Q":
+                    D = 0.5 * (D + D.T)
+                D /= np.linalg.norm(D)
+                fd = gradients.fd_vjp(*prob, kr, gx[i].astype(np.float64), {key: D}, 1e-3, warm)
+                got = float(np.sum(g[key][i].astype(np.float64) * D))
+                bound = pt.GRAD_TOL * np.linalg.norm(g[key][i]) + 1e-4 * abs(fd)
+                worst = max(worst, abs(got - fd) / bound)
+                assert abs(got - fd) <= bound, (i, key, got, fd, bound)
+    print(f"finite differences: worst at {worst:.2f} of its bound", flush=True)

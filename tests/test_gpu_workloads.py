@@ -7,14 +7,15 @@
 * Both centering rules (predictor-corrector and fixed sigma) over a sigma
   sweep reach the same solution.
 
-Tolerances as in test_gpu_parity: x within 1e-4, gradients within 1e-3
-(relative, 2-norm per parameter block).
+Comparisons with the oracle are entry by entry (tests/parity.py).
 """
 import numpy as np
 import pytest
 
 import qpgen
 from oracle import gradients, implicit
+
+import parity as pt
 
 pytestmark = pytest.mark.gpu
 
@@ -35,27 +36,26 @@ def _np(d):
     return {k: (v.cpu().numpy() if not isinstance(v, dict) else _np(v)) for k, v in d.items()}
 
 
-def _grads(P, gx, gy, gz, kr, idx, gtol=1e-3):
+def _grads(P, gx, gy, gz, kr, idx):
     import paper_2605_17913_amd as qpx
     d = _dev()
     Q, q, A, b, G, h = [torch.from_numpy(a).to(d) for a in P.arrays()]
-    sol = qpx.solve(Q, q, A if P.A.shape[1] else None, b if P.A.shape[1] else None, G, h, tol=1e-6)
+    A, b = (A, b) if P.p else (None, None)
+    sol = qpx.solve(Q, q, A, b, G, h)
     t = lambda a: None if a is None else torch.from_numpy(a).to(d)
-    g = qpx.backward(Q, q, A if P.A.shape[1] else None, b if P.A.shape[1] else None, G, h, sol,
-                     t(gx), t(gy), t(gz), kappa_relax=kr, relaxed=True)
+    g = qpx.backward(Q, q, A, b, G, h, sol, t(gx), t(gy), t(gz), kappa_relax=kr, relaxed=True)
     torch.cuda.synchronize()
     g = _np(g)
+    assert np.all(pt.outcome(g["relaxed"]["status"]) == 0)
+    worst = 0.0
     for i in idx:
         ref, rr = gradients.grad_at_relaxed(
             *P.one(i), kr, gx[i].astype(np.float64),
             None if gy is None else gy[i].astype(np.float64),
             None if gz is None else gz[i].astype(np.float64))
-        assert _rel(g["relaxed"]["x"][i], rr.x) <= 1e-4
-        for key in ("Q", "q", "A", "b", "G", "h"):
-            if ref[key].size == 0:
-                continue
-            err = np.linalg.norm(g[key][i] - ref[key]) / max(1e-3, np.linalg.norm(ref[key]))
-            assert err <= gtol, (i, key, err)
+        worst = max(worst, pt.check_point(f"relaxed QP {i}", P, i, g["relaxed"], rr, tol=1e-6))
+        worst = max(worst, pt.check_grads(f"QP {i}", g, i, ref))
+    print(f"  worst entry at {worst:.2f} of its bound", flush=True)
 
 
 @pytest.mark.parametrize("kr", [1e-2, 1e-4])
@@ -82,7 +82,7 @@ def test_safety_filter_batches(na):
     assert np.all((sol["status"] & 0xFF) == 0)
     for i in (0, 100, 255):
         r = implicit.solve_qp(*P.one(i), tol=1e-11, max_iter=200)
-        assert _rel(sol["x"][i], r.x) <= 1e-4, i
+        pt.check_point(f"safety filter N_a={na} QP {i}", P, i, sol, r)
     gx = qpgen.upstream(P.B, 2 * na, seed=3)
     _grads(P, gx, None, None, 1e-4, [0, 255])
 
@@ -97,7 +97,7 @@ def test_centering_rules_agree():
     for pc, sigma in [(True, 0.1), (False, 0.05), (False, 0.1), (False, 0.2), (False, 0.3)]:
         sol = _np(qpx.solve(Q, q, A, b, G, h, pc=pc, sigma=sigma))
         assert np.all((sol["status"] & 0xFF) == 0), (pc, sigma)
-        assert _rel(sol["x"][3], ref.x) <= 1e-4, (pc, sigma)
+        pt.check_point(f"centering pc={pc} sigma={sigma}", P, 3, sol, ref)
         iters[("pc" if pc else f"sigma={sigma}")] = float(sol["iters"].mean())
     print("mean iterations", iters, flush=True)
     # predictor-corrector picks sigma per iteration: no more Newton iterations

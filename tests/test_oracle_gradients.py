@@ -128,3 +128,26 @@ def test_scalar_qp_golden():
         np.testing.assert_allclose(rr.s, [cp["s"]], rtol=1e-10)
         np.testing.assert_allclose(gr["q"], [cp["dx_dq"]], rtol=1e-9)
         np.testing.assert_allclose(gr["h"], [cp["dx_dh"]], rtol=1e-9)
+
+
+def test_ift_matches_finite_differences_at_differentiation_shape():
+    # the differentiation workload's shape (n=100, m=200, p=20), at the step
+    # the workload names for its finite-difference check (1e-3) and at
+    # kappa_relax = 1e-4: central differences of the relaxed map along one
+    # unit-norm random direction per parameter block (symmetric for Q)
+    # agree with the IFT product to better than 1e-4 relative (measured
+    # truncation at this step: <= 6e-5)
+    P = qpgen.make_config("differentiation", seed=0, B=1)
+    prob = P.one(0)
+    gx = qpgen.upstream(1, P.n, seed=11)[0].astype(np.float64)
+    ref, rr = gradients.grad_at_relaxed(*prob, 1e-4, gx)
+    warm = (rr.x, rr.y, rr.z, rr.s)
+    rng = np.random.default_rng(7)
+    for k, key in enumerate(("Q", "q", "A", "b", "G", "h")):
+        D = rng.standard_normal(np.shape(prob[k]))
+        if key == "Q":
+            D = 0.5 * (D + D.T)
+        D /= np.linalg.norm(D)
+        fd = gradients.fd_vjp(*prob, 1e-4, gx, {key: D}, 1e-3, warm)
+        ift = float(np.sum(ref[key] * D))
+        assert abs(fd - ift) <= 1e-4 * max(abs(ift), 1e-3 * np.linalg.norm(ref[key])), (key, fd, ift)
