@@ -29,8 +29,18 @@ def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
 
 
-def _compile(src: str, extra=()) -> str:
+def _newest_dependency() -> float:
+    """Newest modification time of the headers every unit includes."""
+    deps = glob.glob(os.path.join(CSRC, "*.hpp")) + glob.glob(os.path.join(CSRC, "*.h"))
+    deps.append(os.path.join(HERE, "..", "include", "qpx.h"))
+    return max(os.path.getmtime(d) for d in deps)
+
+
+def _compile(src: str, extra=(), incremental: bool = False) -> str:
     obj = os.path.join(OBJ, os.path.basename(src) + ".o")
+    if incremental and os.path.exists(obj) and \
+            os.path.getmtime(obj) > max(os.path.getmtime(src), _newest_dependency()):
+        return obj
     cmd = [HIPCC, *FLAGS, *EXTRA, *extra, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -39,7 +49,9 @@ def _compile(src: str, extra=()) -> str:
 
 
 def build(verbose: bool = False, jobs: int | None = None, out: str | None = None,
-          objdir: str | None = None) -> str:
+          objdir: str | None = None, incremental: bool = False) -> str:
+    """Compile every unit (or, with incremental, only units older than their
+    sources) and link libqpx.so."""
     global OBJ
     if objdir:
         OBJ = objdir
@@ -47,7 +59,7 @@ def build(verbose: bool = False, jobs: int | None = None, out: str | None = None
     srcs = sources()
     jobs = jobs or min(8, os.cpu_count() or 4)
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
+        objs = list(ex.map(lambda src: _compile(src, incremental=incremental), srcs))
     lib = out or LIB
     tmp = lib + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", *objs, "-o", tmp]

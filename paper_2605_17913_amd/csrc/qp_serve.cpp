@@ -20,8 +20,9 @@
 //     iterations), copying their solution from the staging buffer, and
 //     frees their arena space and slot.
 // Lanes complete independently: a bucket of small QPs is retired, refilled
-// and launched again while a bucket of large ones is still running, so a
-// small request's latency does not wait for the largest size class.
+// and launched again while a bucket of large ones is still running, and
+// one lane serves only the small size classes, so a small request's latency
+// does not wait for the largest size class.
 // Requests that arrive while others are on the device join at the next
 // launch of their bucket.  Each QP's arithmetic is independent of the others
 // in its launch, its per-launch iteration budget depends only on its own
@@ -177,12 +178,15 @@ Bucket bucket_of(const Request *r) {
 }
 
 // Launch one bucket of idle resident QPs on lane L.  Called with S->mu held
-// (reads the active list).  Returns false if nothing was launched.
-bool launch_bucket(qpx_server *S, Lane &L) {
+// (reads the active list).  With small_only, only buckets of systems of at
+// most 128 rows qualify.  Returns false if nothing was launched.
+bool launch_bucket(qpx_server *S, Lane &L, bool small_only) {
   // the bucket of the longest-waiting idle QP
   const Request *oldest = nullptr;
   for (const Request *r : S->active)
-    if (!r->in_flight && (!oldest || r->order < oldest->order)) oldest = r;
+    if (!r->in_flight && (!small_only || bucket_of(r).rpl <= 2) &&
+        (!oldest || r->order < oldest->order))
+      oldest = r;
   if (!oldest) return false;
   const Bucket bk = bucket_of(oldest);
   std::vector<Request *> cand;
@@ -324,9 +328,12 @@ void scheduler(qpx_server *S) {
       progress = true;
     }
     S->peak = std::max(S->peak, (int)S->active.size());
-    // launch on idle lanes
-    for (Lane &L : S->lane)
-      if (!L.busy && launch_bucket(S, L)) progress = true;
+    // launch on idle lanes; lane 0 serves only the small size classes, so
+    // their launches (a few milliseconds) never wait behind the large ones
+    for (int li = 0; li < qpx_server::kLanes; ++li) {
+      Lane &L = S->lane[li];
+      if (!L.busy && launch_bucket(S, L, li == 0)) progress = true;
+    }
     bool any_busy = false;
     for (Lane &L : S->lane) any_busy |= L.busy;
     if (!any_busy && S->active.empty() && S->pending.empty() && S->stop) return;
