@@ -201,6 +201,24 @@ int qp_destroy(qpx_ctx *ctx);
 int qp_solve(qpx_ctx *ctx, const qp_batch *batch, const qp_opts *opts,
              qp_out *out, void *stream);
 
+/* Allocation-free qp_solve, for callers that cannot allocate device memory
+ * (code under graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, results and errors as qp_solve, computed by
+ * the same kernels; the factor workspace of QPs whose bordered factor does
+ * not fit LDS is a fixed per-device array of QPX_NOALLOC_SCRATCH_BYTES
+ * (resolved by qp_create; held until the process ends) instead of the
+ * context's growable workspace, and the call makes no allocation.
+ * Errors: QPX_ERR_UNSUPPORTED if the batch needs more workspace than the
+ * array holds (B x qp_plan.workspace_bytes > QPX_NOALLOC_SCRATCH_BYTES: split
+ * the batch); QPX_ERR_STATE if the context's device has no array.  Every
+ * call on one device shares that device's array: calls that overlap in
+ * time on one device (different streams, threads or contexts) race and
+ * must be ordered by the caller.  Nothing in the array needs to start at
+ * zero: the kernels write each factor before reading it. */
+#define QPX_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int qp_solve_noalloc(qpx_ctx *ctx, const qp_batch *batch, const qp_opts *opts,
+                     qp_out *out, void *stream);
+
 /* Backward pass at the relaxed point (sections 2.3 and 5):
  *  1. warm-start from the solution (x, y, z, s) given in `sol` (as written
  *     by qp_solve) and relax to kappa_relax (Algorithm 2);

@@ -76,7 +76,8 @@ class _Plan(ctypes.Structure):
                 ("workspace_bytes", ctypes.c_size_t)]
 
 
-EXPORTS = ["qp_default_opts", "qp_create", "qp_destroy", "qp_solve", "qp_backward",
+EXPORTS = ["qp_default_opts", "qp_create", "qp_destroy", "qp_solve", "qp_solve_noalloc",
+           "qp_backward",
            "qp_status_string", "qp_result_string", "qp_plan_query", "qp_server_create", "qp_serve_submit", "qp_serve_poll",
            "qp_serve_stats", "qp_server_destroy"]
 
@@ -98,6 +99,8 @@ def lib() -> ctypes.CDLL:
             L.qp_destroy.argtypes = [_vp]
             L.qp_solve.argtypes = [_vp, ctypes.POINTER(_Batch), ctypes.POINTER(_Opts),
                                    ctypes.POINTER(_Out), _vp]
+            L.qp_solve_noalloc.argtypes = [_vp, ctypes.POINTER(_Batch), ctypes.POINTER(_Opts),
+                                           ctypes.POINTER(_Out), _vp]
             L.qp_backward.argtypes = [_vp, ctypes.POINTER(_Batch), ctypes.POINTER(_Opts),
                                       ctypes.POINTER(_Out), _vp, _vp, _vp,
                                       ctypes.POINTER(_Grads), ctypes.POINTER(_Out), _vp]
@@ -242,6 +245,25 @@ def solve(Q, q, A, b, G, h, *, opts: _Opts | None = None, work: bool = False, **
     _check(lib().qp_solve(_context(dev), ctypes.byref(st), ctypes.byref(o), ctypes.byref(so),
                           _stream(dev)), "qp_solve")
     return out
+
+
+def solve_noalloc(Q, q, A, b, G, h, out, *, opts: _Opts | None = None, **kw):
+    """qp_solve_noalloc: solve into the caller's preallocated output tensors
+    `out` (dict with x [B,n], y [B,p], z [B,m], s [B,m], status int32 [B] and
+    optionally iters int32 [B], res float32 [B]); the call allocates no
+    device memory (factors that do not fit LDS use the library's fixed
+    per-device workspace of NOALLOC_SCRATCH_BYTES).  Raises QPError if the
+    batch needs more workspace than that."""
+    st, keep, (B, n, m, p, dev) = _batch(Q, q, A, b, G, h)
+    o = opts if opts is not None else make_opts(**kw)
+    so = _Out(_ptr(out["x"]), _ptr(out.get("y")), _ptr(out.get("z")), _ptr(out.get("s")),
+              _ptr(out["status"]), _ptr(out.get("iters")), _ptr(out.get("res")), None)
+    _check(lib().qp_solve_noalloc(_context(dev), ctypes.byref(st), ctypes.byref(o),
+                                  ctypes.byref(so), _stream(dev)), "qp_solve_noalloc")
+    return out
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 def backward(Q, q, A, b, G, h, sol, dl_dx, dl_dy=None, dl_dz=None, *, opts: _Opts | None = None,

@@ -156,6 +156,11 @@ int qp_create(qpx_ctx **ctx, int device) {
   *ctx = nullptr;
   int count = 0;
   if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return QPX_ERR_HIP;
+  // resolve this device's allocation-free workspace (qp_solve_noalloc) while
+  // the device is current
+  if (hipSetDevice(device) != hipSuccess) return QPX_ERR_HIP;
+  int rc = qpk::noalloc_init(device);
+  if (rc) return rc;
   qpx_ctx *c = new (std::nothrow) qpx_ctx();
   if (!c) return QPX_ERR_OOM;
   c->device = device;
@@ -189,20 +194,29 @@ int qp_plan_query(int32_t n, int32_t m, int32_t p, const qp_opts *opts, qp_plan 
   return QPX_OK;
 }
 
-int qp_solve(qpx_ctx *ctx, const qp_batch *bt, const qp_opts *opts, qp_out *out,
-             void *stream) {
+// Checks shared by qp_solve and qp_solve_noalloc; fills the options and
+// the launch plan.  Returns QPX_OK, an error, or QPX_PENDING for B == 0
+// (nothing to do).
+int prepare_solve(qpx_ctx *ctx, const qp_batch *bt, const qp_opts *opts, const qp_out *out,
+                  qp_opts *o, qpk::Plan *pl) {
   if (!ctx || !out) return QPX_ERR_ARG;
   int rc = check_batch(bt);
   if (rc) return rc;
-  qp_opts o;
-  if (opts) o = *opts; else qp_default_opts(&o);
-  if ((rc = check_opts(o))) return rc;
-  if (bt->B == 0) return QPX_OK;
+  if (opts) *o = *opts; else qp_default_opts(o);
+  if ((rc = check_opts(*o))) return rc;
+  if (bt->B == 0) return QPX_PENDING;
   if (!out->x || !out->status) return QPX_ERR_ARG;
   if (bt->p > 0 && !out->y) return QPX_ERR_ARG;
   if (bt->m > 0 && (!out->z || !out->s)) return QPX_ERR_ARG;
+  return qpk::make_plan(bt->n, bt->m, bt->p, *o, pl);
+}
+
+int qp_solve(qpx_ctx *ctx, const qp_batch *bt, const qp_opts *opts, qp_out *out,
+             void *stream) {
+  qp_opts o;
   qpk::Plan pl;
-  if ((rc = qpk::make_plan(bt->n, bt->m, bt->p, o, &pl))) return rc;
+  int rc = prepare_solve(ctx, bt, opts, out, &o, &pl);
+  if (rc) return rc == QPX_PENDING ? QPX_OK : rc;
   if ((rc = set_device(ctx))) return rc;
   hipStream_t st = static_cast<hipStream_t>(stream);
   std::lock_guard<std::mutex> lk(ctx->mu);
@@ -215,6 +229,30 @@ int qp_solve(qpx_ctx *ctx, const qp_batch *bt, const qp_opts *opts, qp_out *out,
   QPK_PHASES("solve", P, st, true);
   const hipError_t e = qpk::launch(P, pl.threads, pl.m_in_lds, pl.lds, bt->B, st);
   QPK_PHASES("solve", P, st, false);
+  return e == hipSuccess ? QPX_OK : QPX_ERR_HIP;
+}
+
+int qp_solve_noalloc(qpx_ctx *ctx, const qp_batch *bt, const qp_opts *opts, qp_out *out,
+                     void *stream) {
+  qp_opts o;
+  qpk::Plan pl;
+  int rc = prepare_solve(ctx, bt, opts, out, &o, &pl);
+  if (rc) return rc == QPX_PENDING ? QPX_OK : rc;
+  // the factors of QPs whose factor does not fit LDS go to this device's
+  // fixed scratch array; a batch that needs more than it holds is refused
+  const size_t need = ws_bytes(pl, bt->B);
+  if (need > (size_t)QPX_NOALLOC_SCRATCH_BYTES) return QPX_ERR_UNSUPPORTED;
+  float *scratch = qpk::noalloc_scratch(ctx->device);
+  if (!scratch) return QPX_ERR_STATE;
+  if ((rc = set_device(ctx))) return rc;
+  qpk::Params P;
+  fill_common(P, bt, o, pl, ctx);
+  P.ws = pl.m_in_lds ? nullptr : scratch;
+  P.x = out->x; P.y = out->y; P.z = out->z; P.s = out->s;
+  P.status = out->status; P.iters = out->iters; P.res = out->res; P.work = out->work;
+  P.mode = qpk::kSolve;
+  const hipError_t e = qpk::launch(P, pl.threads, pl.m_in_lds, pl.lds, bt->B,
+                                   static_cast<hipStream_t>(stream));
   return e == hipSuccess ? QPX_OK : QPX_ERR_HIP;
 }
 

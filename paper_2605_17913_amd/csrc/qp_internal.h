@@ -77,6 +77,10 @@ int64_t ws_floats(int n, int m, int p, int kb);
 bool mfma_stage_fits(int n, int m, int p, int kb, bool m_in_lds, int threads);
 // Largest dynamic LDS per block the kernels may use on this device.
 size_t lds_limit();
+// Allocation-free workspace (qp_noalloc.hip): resolve the current device's
+// copy of the fixed scratch array (once per device), and look it up.
+int noalloc_init(int device);
+float *noalloc_scratch(int device);
 
 // Launch the fused kernel for `P.mode` with `threads` per block.  Returns a
 // hipError_t.
