@@ -38,7 +38,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "QP solves/s + fwd+bwd/s at 1e-5 KKT residual (FP32 vs plain); p50/p99 latency"
 CSRC = os.path.join(ROOT, "paper_2605_17913_amd", "csrc")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_qp_solve_kernel_n50_m100_p10.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_kernels_bench_workloads.json")
 
 PEAK_ALU = 78.6      # TFLOP/s: 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz (FP32 FMA, unpacked)
 PEAK_ALU_PACKED = 157.3
@@ -148,18 +148,21 @@ def kernel_name(kind, n, m, p, **kw):
     return f"qp_{kind}_kernel<{pl['threads']}, {rpl}, {lds}>"
 
 
-def measured_traffic(launch_s):
-    """HBM traffic of the solve kernel from the committed counter runs, or
-    None when the kernel source has changed since they were taken."""
+def measured_traffic(kernel, launch_s):
+    """HBM bytes per launch of `kernel` (FETCH_SIZE + WRITE_SIZE, scaled by a
+    copy of known size) from the committed counter runs, or None when a
+    kernel source has changed since they were taken."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_source_sha256_16") != kernel_source_hash():
+    k = t.get("kernels", {}).get(kernel)
+    if t.get("kernel_source_sha256_16") != kernel_source_hash() or k is None:
         return None
-    byts = t["bytes_per_launch"]
-    return {"bytes_per_launch": byts, "GB_per_s": round(byts / launch_s / 1e9, 1),
+    byts = k["fetch_bytes"] + k["write_bytes"]
+    return {"bytes_per_launch": byts, "fetch_bytes": k["fetch_bytes"],
+            "write_bytes": k["write_bytes"], "GB_per_s": round(byts / launch_s / 1e9, 1),
             "hbm_frac": round(byts / launch_s / 1e9 / PEAK_HBM, 4),
             "source": os.path.basename(TRAFFIC_FILE)}
 
@@ -169,9 +172,11 @@ def grad_bytes(B, n, m, p):
     return 4 * B * (n * n + n + p * n + p + m * n + m)
 
 
-def roofline_entry(kernel, bound, achieved, peak, unit, launch_ms, **extra):
-    return dict(kernel=kernel, bound=bound, achieved=round(achieved, 3), peak=peak, unit=unit,
-                frac=round(achieved / peak, 4), launch_ms=round(launch_ms, 3), **extra)
+def roofline_entry(kernel, bound, achieved, peak, unit, launch_ms, workload="", **extra):
+    return dict(kernel=f"{kernel} {workload}".strip(), bound=bound, achieved=round(achieved, 3),
+                peak=peak, unit=unit, frac=round(achieved / peak, 4),
+                launch_ms=round(launch_ms, 3),
+                traffic=measured_traffic(kernel, launch_ms * 1e-3), **extra)
 
 
 def calibrate_copy(mib=512, reps=5):
@@ -470,16 +475,16 @@ def main():
         "iters_mean": float(np.mean(iters)), "iters_max": int(np.max(iters)),
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_ALU,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_ALU, 4),
-                     "traffic": measured_traffic(fwd_avg),
+                     "traffic": measured_traffic(solve_k, fwd_avg),
                      "kernel": f"{solve_k} (fused solve, one launch per step)",
                      "launch_ms": round(fwd_avg * 1e3, 3), "peak_packed_fp32": PEAK_ALU_PACKED},
     }
     kernels = [
-        roofline_entry(solve_k + " n=50", "alu", achieved, PEAK_ALU, "TFLOP/s", fwd_avg * 1e3),
-        roofline_entry(bwd_k + " n=50", "alu", work_bwd / bwd_avg / 1e12, PEAK_ALU, "TFLOP/s",
-                       bwd_avg * 1e3),
-        roofline_entry(bwd_k + " n=50 (gradient writes, a14)", "hbm",
-                       grad_bytes(B, n, m, p) / bwd_avg / 1e9, PEAK_HBM, "GB/s", bwd_avg * 1e3,
+        roofline_entry(solve_k, "alu", achieved, PEAK_ALU, "TFLOP/s", fwd_avg * 1e3, "n=50"),
+        roofline_entry(bwd_k, "alu", work_bwd / bwd_avg / 1e12, PEAK_ALU, "TFLOP/s",
+                       bwd_avg * 1e3, "n=50"),
+        roofline_entry(bwd_k, "hbm", grad_bytes(B, n, m, p) / bwd_avg / 1e9, PEAK_HBM, "GB/s",
+                       bwd_avg * 1e3, "n=50 (gradient writes, a14)",
                        note="gradient bytes written / whole backward launch (relax + adjoint "
                             "+ writes): a lower bound on the write bandwidth of a14"),
     ]
@@ -522,19 +527,16 @@ def main():
         k3s, k3b = kernel_name("solve", 100, 200, 20), kernel_name("backward", 100, 200, 20)
         k5 = kernel_name("solve", 256, 512, 32)
         kernels += [
-            roofline_entry(k3s + " n=100", "alu", c3["fwd_flops"] / c3["fwd_ms"] / 1e9,
-                           PEAK_ALU, "TFLOP/s", c3["fwd_ms"]),
-            roofline_entry(k3b + " n=100", "alu", c3["bwd_flops"] / c3["bwd_ms"] / 1e9,
-                           PEAK_ALU, "TFLOP/s", c3["bwd_ms"]),
-            roofline_entry(k3b + " n=100 (gradient writes, a14)", "hbm",
-                           grad_bytes(1024, 100, 200, 20) / c3["bwd_ms"] / 1e6, PEAK_HBM, "GB/s",
-                           c3["bwd_ms"]),
-            roofline_entry(k5 + " n=256 FP32 MFMA assembly", "mfma",
-                           c5["fwd_flops"] / c5["fwd_ms"] / 1e9, PEAK_MFMA_FP32, "TFLOP/s",
-                           c5["fwd_ms"]),
-            roofline_entry(k5 + " n=256 BF16x3 assembly", "mfma",
-                           c5b["fwd_flops"] / c5b["fwd_ms"] / 1e9, PEAK_MFMA_FP32, "TFLOP/s",
-                           c5b["fwd_ms"]),
+            roofline_entry(k3s, "alu", c3["fwd_flops"] / c3["fwd_ms"] / 1e9,
+                           PEAK_ALU, "TFLOP/s", c3["fwd_ms"], "n=100"),
+            roofline_entry(k3b, "alu", c3["bwd_flops"] / c3["bwd_ms"] / 1e9,
+                           PEAK_ALU, "TFLOP/s", c3["bwd_ms"], "n=100"),
+            roofline_entry(k3b, "hbm", grad_bytes(1024, 100, 200, 20) / c3["bwd_ms"] / 1e6,
+                           PEAK_HBM, "GB/s", c3["bwd_ms"], "n=100 (gradient writes, a14)"),
+            roofline_entry(k5, "mfma", c5["fwd_flops"] / c5["fwd_ms"] / 1e9, PEAK_MFMA_FP32,
+                           "TFLOP/s", c5["fwd_ms"], "n=256 FP32 MFMA assembly"),
+            roofline_entry(k5, "mfma", c5b["fwd_flops"] / c5b["fwd_ms"] / 1e9, PEAK_MFMA_FP32,
+                           "TFLOP/s", c5b["fwd_ms"], "n=256 BF16x3 assembly"),
         ]
     if not args.no_serving:
         out["serving"] = serving_bench()
