@@ -1119,10 +1119,13 @@ QPK_PHASE int partition_bounded(CT &Cin_, float kappa) {
 // owns up to kAsmTiles 16x16 tiles of the lower triangle per pass and
 // accumulates them over all chunks in FP32.
 //   amode 1 (BF16x3): y = hi + lo with hi = bf16(y), lo = bf16(y - hi);
-//     Y_i'Y_j ~ lo_i'hi_j + hi_i'lo_j + hi_i'hi_j (16x16x16 bf16 MFMA, FP32
-//     accumulation).  The dropped lo'lo term and the rounding of lo leave a
-//     relative error of about 2^-16 per product; the Newton and adjoint
-//     solves refine against the exact operator to recover FP32 accuracy.
+//     Y_i'Y_j ~ hi_i'hi_j + lo_i'hi_j + hi_i'lo_j on gfx950's 16x16x32 bf16
+//     matrix cores with FP32 accumulation: per 16-row chunk one instruction
+//     takes K = 32 as [hi; lo]_i against [hi; hi]_j (the first two terms),
+//     a second [hi; 0]_i against [lo; 0]_j.  The dropped lo'lo term and the
+//     rounding of lo leave a relative error of about 2^-16 per product; the
+//     Newton and adjoint solves refine against the exact operator to
+//     recover FP32 accuracy.
 //   amode 2: FP32 inputs on the 16x16x4 FP32 MFMA.
 // Record layout: amode 1: hi of rows 0..15 as 16 bf16 (floats 0..7), lo as
 // 16 bf16 (floats 8..15); amode 2: rows 0..15 as floats 0..15.  Floats
@@ -1130,9 +1133,7 @@ QPK_PHASE int partition_bounded(CT &Cin_, float kappa) {
 // fragment load touches over the LDS banks.
 constexpr int kStgRec = 20;
 constexpr int kAsmTiles = 9;
-typedef short s4v __attribute__((ext_vector_type(4)));
-typedef unsigned u2v __attribute__((ext_vector_type(2)));
-typedef __attribute__((address_space(3))) u2v lu2;
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 typedef __attribute__((address_space(3))) unsigned lu;
 
 QPD unsigned bf16_pair(float a, float b) {
@@ -1201,13 +1202,20 @@ QPD void assemble_h_mfma(CT &C, int ne, const lf *wts) {
         const lf *ra = stg + (16 * ti[j] + c16) * kStgRec;
         const lf *rb = stg + (16 * tj[j] + c16) * kStgRec;
         if (bf) {
-          const s4v ah = __builtin_bit_cast(s4v, *reinterpret_cast<const lu2 *>(ra + 2 * g));
-          const s4v al = __builtin_bit_cast(s4v, *reinterpret_cast<const lu2 *>(ra + 8 + 2 * g));
-          const s4v bh = __builtin_bit_cast(s4v, *reinterpret_cast<const lu2 *>(rb + 2 * g));
-          const s4v bl = __builtin_bit_cast(s4v, *reinterpret_cast<const lu2 *>(rb + 8 + 2 * g));
-          acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc[j], 0, 0, 0);
-          acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc[j], 0, 0, 0);
-          acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc[j], 0, 0, 0);
+          // lane group g holds K = 8g .. 8g+7 of its row (A) or column (B);
+          // a record's 16-byte quarters are hi rows 0-7, hi 8-15, lo 0-7,
+          // lo 8-15
+          const lf4 *RA = reinterpret_cast<const lf4 *>(ra);
+          const lf4 *RB = reinterpret_cast<const lf4 *>(rb);
+          const f4v zero = {0.f, 0.f, 0.f, 0.f};
+          const f4v a1 = RA[g], b1 = RB[g & 1];
+          const f4v a2 = g < 2 ? RA[g] : zero, b2 = g < 2 ? RB[2 + g] : zero;
+          acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8v, a1),
+                                                          __builtin_bit_cast(bf8v, b1), acc[j],
+                                                          0, 0, 0);
+          acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8v, a2),
+                                                          __builtin_bit_cast(bf8v, b2), acc[j],
+                                                          0, 0, 0);
         } else {
           const f4v a = *reinterpret_cast<const lf4 *>(ra + 4 * g);
           const f4v b = *reinterpret_cast<const lf4 *>(rb + 4 * g);
