@@ -1481,22 +1481,25 @@ QPD float maxnorm(const lf *r, int N, lf *red) {
 // taken back and ends the refinement.  Returns the contraction of the first
 // correction (residual max-norm after it over the one before; kBig for a
 // non-finite residual): above 1/2 the factor is too coarse a
-// preconditioner in this arithmetic.
+// preconditioner in this arithmetic.  iflag[7] receives the residual
+// max-norm of the returned u (float bits).
 template <int T, int RPL, class AT, class CT>
 QPK_PHASE float refine(CT &Cin_, int nb, bool bounded, const lf *w, lf *u, int steps) {
   CT C = uctx(Cin_);
   nb = rfl(nb); bounded = rfl(bounded); w = rflp(w); u = rflp(u); steps = rfl(steps);
   const int n = C.n, p = C.p, tid = threadIdx.x, N = n + nb + p;
   lf *r = C.rr;
-  float prev = 0.f, first = 0.f;
+  float prev = 0.f, first = 0.f, cur = 0.f;
   for (int it = 0; it <= steps; ++it) {
     kkt_apply<T, AT>(C, nb, bounded, w, u, r, true);
     const float nrm = maxnorm<T>(r, N, C.red);
+    cur = nrm;
     if (it > 0) {
       if (it == 1) first = prev > 0.f ? nrm / prev : 0.f;
       if (!(nrm < prev)) {
         // the last correction did not help: take it back and stop
         for (int j = tid; j < N; j += T) u[j] -= C.rd[j];
+        cur = prev;
         __syncthreads();
         break;
       }
@@ -1513,6 +1516,8 @@ QPK_PHASE float refine(CT &Cin_, int nb, bool bounded, const lf *w, lf *u, int s
     }
     __syncthreads();
   }
+  if (threadIdx.x == 0) C.iflag[7] = __float_as_int(cur);
+  __syncthreads();
   return first;
 }
 
@@ -2101,7 +2106,13 @@ QPD int newton_loop(CT &C, bool bounded, int max_iter, float tol, int kt_mode, f
       iters = it;
       break;
     }
-    if (it >= max_iter) { status = ST_MAXIT; iters = it; break; }
+    if (it >= max_iter) {
+      // an iteration limit inside Algorithm 2 is reported at the relax stage
+      status = ST_MAXIT;
+      if (kt_mode == 2) stage = SG_RELAX;
+      iters = it;
+      break;
+    }
     int st;
     if (bounded)
       st = newton_bounded<T, RPL>(C, kappa, kt_mode, sigma, kr, delta_reg, refine_steps, work, &stage);
@@ -2131,8 +2142,15 @@ QPD void load_vectors(CT &C) {
 
 // Factor at the current (relaxed) point and solve the adjoint system for
 // the upstream gradient; returns dx in u0[0:n], dy in u0[n+nb:], dz in dv0.
+// Returns kAdjOk, kAdjFactorFail, or kAdjInaccurate when the refinement of
+// the adjoint solve stalled (contraction above 1/2 in the last arithmetic
+// it used) with a residual above kAdjResTol of the right-hand side: the
+// factor is too coarse a preconditioner for this system and the gradient
+// is not reliable.
+constexpr int kAdjOk = 0, kAdjFactorFail = 1, kAdjInaccurate = 2;
+constexpr float kAdjResTol = 1e-5f;
 template <int T, int RPL, class CT>
-QPK_PHASE bool adjoint(CT &Cin_, bool bounded, const gf *gx, const gf *gy, const gf *gz,
+QPK_PHASE int adjoint(CT &Cin_, bool bounded, const gf *gx, const gf *gy, const gf *gz,
                  float delta_reg, int refine_steps, double &work) {
   CT C = uctx(Cin_);
   bounded = rfl(bounded); gx = rflp(gx); gy = rflp(gy); gz = rflp(gz);
@@ -2168,7 +2186,7 @@ QPK_PHASE bool adjoint(CT &Cin_, bool bounded, const gf *gx, const gf *gy, const
   const double dn = n, dN = N;
   const double wfac = (double)ne * dn * (dn + 1.0) + dN * dN * dN / 3.0 + 2.0 * dN * dN + 8.0 * m * dn;
   const double wstep = 2.0 * dN * dN + 2.0 * dn * dn + 8.0 * m * dn + 4.0 * p * dn;
-  bool ok = false;
+  bool ok = false, inaccurate = false;
   if (bounded) {
     C.amode = rfl(C.iflag[3]);
     // as in newton_bounded: fall back from split-product assembly when the
@@ -2192,8 +2210,11 @@ QPK_PHASE bool adjoint(CT &Cin_, bool bounded, const gf *gx, const gf *gy, const
       rhs_bounded<T>(C, nb, kappa, gx, gz, gy, true);
       for (int j = tid; j < N; j += T) C.w0[j] = C.u0[j];
       __syncthreads();
+      const float wn = maxnorm<T>(C.w0, N, C.red);
       solve2<T, RPL>(C, N, false);
       const float q = nref ? refine_policy<T, RPL>(C, nb, true, C.w0, C.u0, nref) : 0.f;
+      inaccurate = nref && !(q <= kRefineSlow) &&
+                   !(__int_as_float(C.iflag[7]) <= kAdjResTol * wn);
       if (C.amode == 1 && !(q <= kRefineSlow)) {
         C.amode = 2;
         if (tid == 0) C.iflag[3] = 2;
@@ -2206,7 +2227,7 @@ QPK_PHASE bool adjoint(CT &Cin_, bool bounded, const gf *gx, const gf *gy, const
       }
       break;
     }
-    if (!ok) return false;
+    if (!ok) return kAdjFactorFail;
     recover_bounded<T>(C, nb, false);
     // dz = E (dv + gz)
     for (int i = tid; i < m; i += T) C.dv0[i] = C.E[i] * (C.dv0[i] + (gz ? gz[i] : 0.f));
@@ -2215,7 +2236,7 @@ QPK_PHASE bool adjoint(CT &Cin_, bool bounded, const gf *gx, const gf *gy, const
     ok = signed_cholesky<T, RPL>(C.M, N, n, C.iflag, false);
     const int nref = plain_refine_steps(C.rmode, refine_steps, 2);
     work += wfac + nref * wstep;
-    if (!ok) return false;
+    if (!ok) return kAdjFactorFail;
     make_dinv<T>(C, N);
     // standard: [H A'; A 0][a; c] = [-gx - G' W gz; -gy], dz = W (G a + gz)
     for (int i = tid; i < m; i += T) C.t0[i] = gz ? C.E[i] * gz[i] : 0.f;
@@ -2228,8 +2249,12 @@ QPK_PHASE bool adjoint(CT &Cin_, bool bounded, const gf *gx, const gf *gy, const
     for (int i = tid; i < n; i += T) C.u0[i] = C.w0[i] = -gx[i] - (m ? C.tGz[i] : 0.f);
     for (int k = tid; k < p; k += T) C.u0[n + k] = C.w0[n + k] = gy ? -gy[k] : 0.f;
     __syncthreads();
+    const float wn = maxnorm<T>(C.w0, N, C.red);
     solve2<T, RPL>(C, N, false);
-    if (nref) refine_policy<T, RPL>(C, 0, false, C.w0, C.u0, nref);
+    if (nref) {
+      const float q = refine_policy<T, RPL>(C, 0, false, C.w0, C.u0, nref);
+      inaccurate = !(q <= kRefineSlow) && !(__int_as_float(C.iflag[7]) <= kAdjResTol * wn);
+    }
     if (m) {
       const lf *xv[1] = {C.u0};
       lf *o[1] = {C.t0};
@@ -2257,7 +2282,7 @@ QPK_PHASE bool adjoint(CT &Cin_, bool bounded, const gf *gx, const gf *gy, const
       __syncthreads();
     }
   }
-  return true;
+  return inaccurate ? kAdjInaccurate : kAdjOk;
 }
 
 // Write the parameter gradients of Algorithm 3 with coalesced stores.
@@ -2462,11 +2487,14 @@ QPD void qp_body(const Params &P) {
     const gf *gx = (const gf *)P.gx + qi * (size_t)n;
     const gf *gy = P.gy ? (const gf *)P.gy + qi * (size_t)p : nullptr;
     const gf *gz = P.gz ? (const gf *)P.gz + qi * (size_t)m : nullptr;
-    const bool ok = adjoint<T, RPL>(C, bounded, gx, gy, gz, P.delta_reg, refine, work);
+    const int adj = adjoint<T, RPL>(C, bounded, gx, gy, gz, P.delta_reg, refine, work);
     QPK_PT(C, PH_BWD);
     // Algorithm 2 hands the factorisation at the relaxed point to the
-    // gradient computation, so a breakdown there counts as a relax failure
-    if (!ok) status = mkstatus(ST_FACT, SG_RELAX);
+    // gradient computation, so a breakdown there counts as a relax failure;
+    // an adjoint solve whose refinement stalled is reported at the backward
+    // stage (the gradients are written but not reliable)
+    if (adj == kAdjFactorFail) status = mkstatus(ST_FACT, SG_RELAX);
+    else if (adj == kAdjInaccurate && (status & 0xff) == ST_CONV) status = mkstatus(ST_MAXIT, SG_BWD);
     __syncthreads();
     write_grads<T>(C, P, qi);
     if (P.rx) for (int i = tid; i < n; i += T) ((gf *)P.rx)[qi * n + i] = C.x[i];

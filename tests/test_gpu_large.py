@@ -143,3 +143,28 @@ def test_workspace_shared_across_streams():
         torch.cuda.synchronize()
         assert np.array_equal(a["x"].cpu().numpy(), ref1)
         assert np.array_equal(b["x"].cpu().numpy(), ref2)
+
+
+def test_ill_conditioned_tight_relaxation_is_reported():
+    # at kappa_relax = 1e-4 the relaxed system of this workload is beyond an
+    # FP32 factorisation (its Schur complement has a condition number of
+    # about 2e8): the library must say so.  Every QP either reports a
+    # converged relaxation with gradients within the tolerance, or reports
+    # that the relaxation or the adjoint solve did not converge (iteration
+    # limit, at the relax or backward stage).
+    import paper_2605_17913_amd as qpx
+    kr = 1e-4
+    P = qpgen.ill_conditioned(4, 256, 512, 32, seed=1)
+    T = pt.to_dev(P)
+    sol = qpx.solve(*T, tol=C5_TOL)
+    gx = qpgen.upstream(P.B, 256, seed=2)
+    g = pt.npd(qpx.backward(*T, sol, torch.from_numpy(gx).to(T[0].device), kappa_relax=kr,
+                            relaxed=True))
+    rst = g["relaxed"]["status"]
+    print("  relaxed status:", [qpx.result_string(int(s)) for s in rst], flush=True)
+    for i in range(P.B):
+        if pt.outcome(rst[i]) == 0:
+            ref, _ = gradients.grad_at_relaxed(*P.one(i), kr, gx[i].astype(np.float64))
+            pt.check_grads(f"converged relaxation QP {i}", g, i, ref)
+        else:
+            assert pt.outcome(rst[i]) == 1 and ((rst[i] >> 8) & 0xFF) in (6, 7), rst[i]
