@@ -85,6 +85,10 @@ template <> struct Vec4<lf> { typedef lf4 type; };
 template <> struct Vec4<gf> { typedef gf4 type; };
 template <> struct Vec4<const lf> { typedef const lf4 type; };
 template <> struct Vec4<const gf> { typedef const gf4 type; };
+typedef float f2v __attribute__((ext_vector_type(2)));
+template <class F> struct Vec2;
+template <> struct Vec2<lf> { typedef const __attribute__((address_space(3))) f2v type; };
+template <> struct Vec2<gf> { typedef const __attribute__((address_space(1))) f2v type; };
 
 QPD bool finitef(float a) { return fabsf(a) <= FLT_MAX; }
 
@@ -240,7 +244,7 @@ __host__ __device__ inline Layout make_layout(int n, int m, int p, int kb, bool 
   const int tlen = max(max(m, p), L.Nmax);  // t0/t1 also hold refinement rhs copies
   L.t0 = take(tlen); L.t1 = take(tlen);
   L.u0 = take(L.Nmax); L.u1 = take(L.Nmax);
-  L.dv0 = take(m); L.dv1 = take(m); L.dinv = take(L.Nmax);
+  L.dv0 = take(m); L.dv1 = take(m); L.dinv = take((L.Nmax + 15) & ~15);
   // partial sums (2 floats or 1 double per thread) and reduction scratch
   L.part = take(2 * T); L.red = take((T / 64) * 16);
   L.w0 = L.t0; L.w1 = L.t1; L.rr = take(L.Nmax); L.rd = take(L.Nmax);
@@ -471,16 +475,20 @@ constexpr float kPivTol = 1e-6f;
 constexpr float kPivReg = 1e-5f;
 constexpr float kGrowthMax = 1e2f;  // accepted max|L| / sqrt(largest pivot) with
                                     // replacements (a stable factor stays near 1)
-template <int RPL, class MF>
-QPD bool factor_panel(MF *M, int N, int npos, int k0, bool dyn, float &pmax, int &nreg,
-                      float &lmax) {
-  constexpr int GRP = RPL - 1 < 4 ? RPL - 1 : 4;
+// The panel's first sweep with G extra 64-row chunks in registers (rows
+// k0 + lane + 64 (1 + g)); P0 holds chunk 0 (the diagonal block) on return
+// and iv the signed pivot inverses, for the replay of any further chunks.
+// The multipliers of column jj are read from ps = a[.][jj] / L[jj][jj],
+// which equals L[.][jj] sg_jj exactly (the sign is folded into the
+// broadcast source instead of into every multiplier).
+template <int G, class MF>
+QPD bool panel_sweep(MF *M, int N, int npos, int k0, int kb, bool dyn, float &pmax, int &nreg,
+                     float &lmax, float (&P0)[kNB], float (&iv)[kNB]) {
   const int lane = threadIdx.x & 63;
-  const int kb = min(kNB, N - k0);
-  float P0[kNB], P[GRP > 0 ? GRP : 1][kNB], iv[kNB];
+  float P[G > 0 ? G : 1][kNB];
   panel_load(M, N, k0, k0 + lane, P0);
 #pragma unroll
-  for (int g = 0; g < GRP; ++g) panel_load(M, N, k0, k0 + lane + 64 * (1 + g), P[g]);
+  for (int g = 0; g < G; ++g) panel_load(M, N, k0, k0 + lane + 64 * (1 + g), P[g]);
   bool fail = false;
 #pragma unroll
   for (int jj = 0; jj < kNB; ++jj) {
@@ -502,21 +510,58 @@ QPD bool factor_panel(MF *M, int N, int npos, int k0, bool dyn, float &pmax, int
       const float d = ok ? tt * rs : 1.f;
       const float inv = sg * rs;
       iv[jj] = inv;
-      P0[jj] = lane > jj ? P0[jj] * inv : (lane == jj ? d : P0[jj]);
+      const float ps = P0[jj] * rs;  // L[k0+lane][k0+jj] sg below the diagonal
+      P0[jj] = lane > jj ? ps * sg : (lane == jj ? d : P0[jj]);
 #pragma unroll
-      for (int g = 0; g < GRP; ++g) P[g][jj] *= inv;
+      for (int g = 0; g < G; ++g) P[g][jj] *= inv;
 #pragma unroll
       for (int cc = jj + 1; cc < kNB; ++cc) {
-        const float lc = readlane(P0[jj], cc) * sg;  // L[k0+cc][k0+jj] sg
+        const float lc = readlane(ps, cc);  // L[k0+cc][k0+jj] sg
         P0[cc] = fmaf(-P0[jj], lc, P0[cc]);
 #pragma unroll
-        for (int g = 0; g < GRP; ++g) P[g][cc] = fmaf(-P[g][jj], lc, P[g][cc]);
+        for (int g = 0; g < G; ++g) P[g][cc] = fmaf(-P[g][jj], lc, P[g][cc]);
       }
     }
   }
   panel_store(M, N, k0, k0 + lane, P0, lmax);
 #pragma unroll
-  for (int g = 0; g < GRP; ++g) panel_store(M, N, k0, k0 + lane + 64 * (1 + g), P[g], lmax);
+  for (int g = 0; g < G; ++g) panel_store(M, N, k0, k0 + lane + 64 * (1 + g), P[g], lmax);
+  return fail;
+}
+
+// The first sweep with as many extra chunks as hold rows of the system
+// (gact), from G down: chunks entirely past row N-1 would only carry zeros.
+template <int G, class MF>
+QPD bool panel_sweep_upto(int gact, MF *M, int N, int npos, int k0, int kb, bool dyn,
+                          float &pmax, int &nreg, float &lmax, float (&P0)[kNB],
+                          float (&iv)[kNB]) {
+  if constexpr (G == 0) {
+    return panel_sweep<0>(M, N, npos, k0, kb, dyn, pmax, nreg, lmax, P0, iv);
+  } else {
+    if (gact >= G) return panel_sweep<G>(M, N, npos, k0, kb, dyn, pmax, nreg, lmax, P0, iv);
+    return panel_sweep_upto<G - 1>(gact, M, N, npos, k0, kb, dyn, pmax, nreg, lmax, P0, iv);
+  }
+}
+
+// The panel factorisation (see above).
+template <int RPL, class MF>
+QPD bool factor_panel(MF *M, int N, int npos, int k0, bool dyn, float &pmax, int &nreg,
+                      float &lmax) {
+  constexpr int GRP = RPL - 1 < 4 ? RPL - 1 : 4;
+  const int lane = threadIdx.x & 63;
+  const int kb = min(kNB, N - k0);
+  float P0[kNB], iv[kNB];
+  bool fail;
+  if constexpr (GRP <= 3) {
+    // extra chunks that hold rows of the system (uniform)
+    const int gact = min(GRP, (N - k0 - 1) >> 6);
+    fail = panel_sweep_upto<GRP>(gact, M, N, npos, k0, kb, dyn, pmax, nreg, lmax, P0, iv);
+  } else {
+    fail = panel_sweep<GRP>(M, N, npos, k0, kb, dyn, pmax, nreg, lmax, P0, iv);
+  }
+  // rows past the first 64 (1 + GRP): replay the eliminations with the
+  // finished diagonal block, GRP chunks at a time
+  float P[GRP > 0 ? GRP : 1][kNB];
 #pragma unroll 1
   for (int t0 = 1 + GRP; t0 < RPL; t0 += GRP) {
     if (k0 + 64 * t0 >= N) break;
@@ -611,6 +656,39 @@ QPK_PHASE bool signed_cholesky(MF *M, int N, int npos, li *flag, bool dyn) {
   return flag[0] == 0;
 }
 
+// dv[c] = dinv[c] for c < CW (CW a multiple of 4) as 16-byte loads; dinv
+// is allocated in whole 16-entry blocks, and entries past the system's last
+// row are never used.
+template <int CW>
+QPD void load_dinv(const lf *dinv, float (&dv)[CW]) {
+#pragma unroll
+  for (int c = 0; c < CW; c += 4) {
+    const f4v v4 = *reinterpret_cast<const lf4 *>(dinv + c);
+    dv[c] = v4.x; dv[c + 1] = v4.y; dv[c + 2] = v4.z; dv[c + 3] = v4.w;
+  }
+}
+
+// o[t] = p[t] for t < RPL (p aligned to RPL floats) if `in`, else zeros, as
+// one vector load for RPL <= 4 (16-byte loads above).
+template <int RPL, class MF>
+QPD void load_run(const MF *p, bool in, float (&o)[RPL]) {
+  if constexpr (RPL == 1) {
+    o[0] = in ? p[0] : 0.f;
+  } else if constexpr (RPL == 2) {
+    f2v v = {0.f, 0.f};
+    if (in) v = *reinterpret_cast<const typename Vec2<MF>::type *>(p);
+    o[0] = v.x; o[1] = v.y;
+  } else {
+    typedef typename Vec4<const MF>::type CV4;
+#pragma unroll
+    for (int t = 0; t < RPL; t += 4) {
+      f4v v = {0.f, 0.f, 0.f, 0.f};
+      if (in) v = *reinterpret_cast<CV4 *>(p + t);
+      o[t] = v.x; o[t + 1] = v.y; o[t + 2] = v.z; o[t + 3] = v.w;
+    }
+  }
+}
+
 // Solve (L diag(sg) L') u = r in place for one right-hand side held in
 // `r` (length N), by a single wave with the vector in registers (lane owns
 // rows RPL*lane + t).  The forward sweep walks rows of L, the backward sweep
@@ -656,8 +734,7 @@ QPD void signed_solve_wave(const MF *M, int N, int npos, const lf *dinv, lf *r, 
           Lc[t][c] = v4.x; Lc[t][c + 1] = v4.y; Lc[t][c + 2] = v4.z; Lc[t][c + 3] = v4.w;
         }
       }
-#pragma unroll
-      for (int c = 0; c < CW; ++c) dv[c] = dinv[min(j0 + h + c, N - 1)];
+      load_dinv<CW>(dinv + j0 + h, dv);
 #pragma unroll
       for (int c = 0; c < CW; ++c) {
         const int j = j0 + h + c;
@@ -682,19 +759,22 @@ QPD void signed_solve_wave(const MF *M, int N, int npos, const lf *dinv, lf *r, 
 #pragma unroll
     for (int h = kNB - CW; h >= 0; h -= CW) {
       float Lr[RPL][CW], dv[CW];
+      // rows b0 .. b0+15 are one block: row b0+c starts c * rstride floats
+      // after row b0 (the last rows, past N-1, read row N-1)
+      const int rstride = 20 + 16 * (b0 >> 4);
+      const MF *brow = M + moff(b0) + RPL * lane;
+      // rows above the block read row j; rows in the block read row j's
+      // zero padding right of its diagonal; rows below read zeros.  A lane's
+      // RPL rows are all above the block or all at or below it.
+      const bool above = RPL * lane < b0 + kNB;
 #pragma unroll
       for (int c = 0; c < CW; ++c) {
-        const int j = min(b0 + h + c, N - 1);
-        const MF *row = M + moff(j);
+        float run[RPL];
+        load_run<RPL>(brow + min(h + c, N - 1 - b0) * rstride, above, run);
 #pragma unroll
-        for (int t = 0; t < RPL; ++t) {
-          const int i = RPL * lane + t;
-          // rows above the block read row j; rows in the block read row j's
-          // zero padding right of its diagonal; rows below read zeros
-          Lr[t][c] = i < b0 + kNB ? row[i] : 0.f;
-        }
-        dv[c] = dinv[j];
+        for (int t = 0; t < RPL; ++t) Lr[t][c] = run[t];
       }
+      load_dinv<CW>(dinv + b0 + h, dv);
 #pragma unroll
       for (int c = CW - 1; c >= 0; --c) {
         const int j = b0 + h + c;
@@ -1079,16 +1159,25 @@ QPK_PHASE int partition_bounded(CT &Cin_, float kappa) {
   }
   if (nb > kb) {
     // more candidates than border slots: keep the kb largest v (ties by row
-    // index) and eliminate the rest
+    // index) and eliminate the rest.  The rank of row i counts the rows
+    // ahead of it; v is read four rows per 16-byte broadcast load, several
+    // loads in flight, and the padding past row m is masked.
     li *cand = C.role;
+    const lf4 *v4 = reinterpret_cast<const lf4 *>(C.v);
+    const int m4 = (m + 3) >> 2;
     for (int i = tid; i < m; i += T) {
       int f = 0;
       const float vi = C.v[i];
       if (vi > 0.f) {
         int rank = 0;
-        for (int j = 0; j < m; ++j) {
-          const float vj = C.v[j];
-          rank += (vj > vi) || (vj == vi && j < i);
+        auto ahead = [&](float vj, int j) {
+          return (int)(j < m && ((vj > vi) || (vj == vi && j < i)));
+        };
+#pragma unroll 4
+        for (int q = 0; q < m4; ++q) {
+          const f4v w4 = v4[q];
+          rank += ahead(w4.x, 4 * q) + ahead(w4.y, 4 * q + 1) + ahead(w4.z, 4 * q + 2) +
+                  ahead(w4.w, 4 * q + 3);
         }
         f = rank < kb;
       }
