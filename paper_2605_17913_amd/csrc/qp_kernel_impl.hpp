@@ -142,9 +142,78 @@ QPD void wave_sync() {
 enum Phase { PH_INIT, PH_RESID, PH_PART, PH_ASM, PH_FACT, PH_RHS, PH_SOLVE, PH_REFINE,
              PH_RECOVER, PH_STEP, PH_BWD, PH_OUT, PH_N = 16 };
 
-struct OpSum { QPD static float f(float a, float b) { return a + b; } };
+struct OpSum { template <class V> QPD static V f(V a, V b) { return a + b; } };
 struct OpMax { QPD static float f(float a, float b) { return fmaxf(a, b); } };
 struct OpMin { QPD static float f(float a, float b) { return fminf(a, b); } };
+
+// One butterfly step: Op(v, value of lane ^ O) in every lane, on the VALU
+// (DPP row rotations, gfx950's permlane swaps) instead of the LDS crossbar
+// that shuffles use; V is float or double (two 32-bit halves).  Steps run
+// in descending O: once the steps above O have run, lanes l and l ^ 2^k
+// (2^k > O) hold equal values, so the rotation by O within a 16-lane row,
+// which reaches lane (l - O) mod 16, reads the value of lane l ^ O (for
+// O = 8 it is that lane); the swaps exchange whole rows (O = 16) or halves
+// (O = 32) exactly.  With commutative operations the results are bitwise
+// those of the shuffle butterfly.  All lanes of the wave must be active.
+template <int O>
+QPD int dpp_ror(int v) {
+  static_assert(O == 8 || O == 4 || O == 2 || O == 1, "row rotation");
+  return __builtin_amdgcn_update_dpp(0, v, 0x120 + O, 0xF, 0xF, false);  // row_ror:O
+}
+template <int O>
+QPD void lane_swap(int v, int &a, int &b) {
+  if constexpr (O == 32) {
+    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    a = r[0]; b = r[1];
+  } else {
+    static_assert(O == 16, "row swap");
+    const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    a = r[0]; b = r[1];
+  }
+}
+template <int O, class Op, class V>
+QPD V bfly(V v) {
+  if constexpr (sizeof(V) == 4) {
+    const int iv = __float_as_int(v);
+    if constexpr (O >= 16) {
+      int a, b;
+      lane_swap<O>(iv, a, b);
+      return Op::f(__int_as_float(a), __int_as_float(b));
+    } else {
+      return Op::f(v, __int_as_float(dpp_ror<O>(iv)));
+    }
+  } else {
+    const long long w = __double_as_longlong(v);
+    const int lo = (int)(unsigned)w, hi = (int)(unsigned)(w >> 32);
+    auto join = [](int l, int h) {
+      return __longlong_as_double((long long)(((unsigned long long)(unsigned)h << 32) |
+                                              (unsigned)l));
+    };
+    if constexpr (O >= 16) {
+      int al, bl, ah, bh;
+      lane_swap<O>(lo, al, bl);
+      lane_swap<O>(hi, ah, bh);
+      return Op::f(join(al, ah), join(bl, bh));
+    } else {
+      return Op::f(v, join(dpp_ror<O>(lo), dpp_ror<O>(hi)));
+    }
+  }
+}
+// Op over the 16 lanes of each row, in every lane.
+template <class Op, class V>
+QPD V row_bfly(V v) {
+  v = bfly<8, Op>(v);
+  v = bfly<4, Op>(v);
+  v = bfly<2, Op>(v);
+  return bfly<1, Op>(v);
+}
+// Op over the wave, in every lane.
+template <class Op, class V>
+QPD V wave_bfly(V v) {
+  v = bfly<32, Op>(v);
+  v = bfly<16, Op>(v);
+  return row_bfly<Op>(v);
+}
 
 // Reduce K values across the workgroup; every thread gets the results.
 // `red` needs (T/64)*K floats.  Contains two barriers.
@@ -152,8 +221,7 @@ template <int T, class Op, int K>
 QPD void block_reduce(float (&v)[K], lf *red) {
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v[k] = Op::f(v[k], __shfl_xor(v[k], o, 64));
+    v[k] = wave_bfly<Op>(v[k]);
   }
   if constexpr (T > 64) {
     const int w = threadIdx.x >> 6;
@@ -312,8 +380,7 @@ QPD void rowdot(const RF *R, int ld, int rows, int cols, const lf *const (&x)[NV
         acc[k] = 0.f;
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[k] = fmaf(e[c], xv[k][c], acc[k]);
-#pragma unroll
-        for (int o = 8; o > 0; o >>= 1) acc[k] += __shfl_xor(acc[k], o, 16);
+        acc[k] = row_bfly<OpSum>(acc[k]);
       }
       if (sub == 0 && i < rows) {
 #pragma unroll
@@ -363,8 +430,7 @@ QPD void coldot(const RF *R, int ld, int rows, int cols, const lf *const (&x)[NV
     for (int k = 0; k < NV; ++k)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        c[k][q] += __shfl_xor(c[k][q], 16, 64);
-        c[k][q] += __shfl_xor(c[k][q], 32, 64);
+        c[k][q] = bfly<32, OpSum>(bfly<16, OpSum>(c[k][q]));
       }
     if ((tid & 63) < 16) {
 #pragma unroll
@@ -641,8 +707,7 @@ QPK_PHASE bool signed_cholesky(MF *M, int N, int npos, li *flag, bool dyn) {
     __syncthreads();
   }
   if (wid == 0) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) lmax = fmaxf(lmax, __shfl_xor(lmax, o, 64));
+    lmax = wave_bfly<OpMax>(lmax);
     // with regularised pivots, entries of L far beyond the scale sqrt(pmax)
     // of a stable factor mean the replaced pivots amplified rounding errors:
     // report a failure so the caller factors again with a uniform floor
@@ -876,8 +941,7 @@ QPD void kkt_matvecs(const gf *Q, const gf *G, const gf *A, int n, int m, int p,
           if (dots) d = fma((AT)e[k], xv[k], d);
         }
         if (dots) {
-#pragma unroll
-          for (int o = 8; o > 0; o >>= 1) d += __shfl_xor(d, o, 16);
+          d = row_bfly<OpSum>(d);
           if (sub == 0 && i < rows) out[i] = jb ? out[i] + d : d;
         }
       }
@@ -889,8 +953,7 @@ QPD void kkt_matvecs(const gf *Q, const gf *G, const gf *A, int n, int m, int p,
     auto reduce = [&](AT(&c)[4], bool first, float &mx) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        c[k] += __shfl_xor(c[k], 16, 64);
-        c[k] += __shfl_xor(c[k], 32, 64);
+        c[k] = bfly<32, OpSum>(bfly<16, OpSum>(c[k]));
       }
       if ((tid & 63) < 16) {
 #pragma unroll
