@@ -76,6 +76,10 @@ int64_t ws_floats(int n, int m, int p, int kb);
 // Whether the matrix-core assembly's LDS staging fits the per-QP layout.
 bool mfma_stage_fits(int n, int m, int p, int kb, bool m_in_lds, int threads);
 // Largest dynamic LDS per block the kernels may use on this device.
+// LDS of a CU, the kernels' static LDS (context table, profiling counters;
+// an upper bound) and the most dynamic LDS one QP may take.
+constexpr size_t kCuLds = 160 * 1024;
+constexpr size_t kStaticLds = 512;
 size_t lds_limit();
 // Allocation-free workspace (qp_noalloc.hip): resolve the current device's
 // copy of the fixed scratch array (once per device), and look it up.
@@ -123,10 +127,10 @@ inline int make_plan(int n, int m, int p, const qp_opts &o, Plan *pl) {
   // factor that fits LDS but halves (or worse) the residency of the
   // global-factor layout goes to global memory instead: at n = 100 the LDS
   // factor leaves one QP per CU, the global one three (15% faster).
-  const size_t cu_lds = lim;
+  const size_t cu_lds = qpk::kCuLds;
   const int cu_waves = 4 * (T >= 512 ? 2 : 3);
   auto per_cu = [&](size_t bytes) {
-    return std::min<size_t>(cu_lds / std::max<size_t>(bytes, 1), cu_waves / (T / 64));
+    return std::min<size_t>(cu_lds / (bytes + qpk::kStaticLds), cu_waves / (T / 64));
   };
   const bool fits = with_m <= lim;
   const bool prefer_global =

@@ -542,14 +542,16 @@ constexpr float kPivReg = 1e-5f;
 constexpr float kGrowthMax = 1e2f;  // accepted max|L| / sqrt(largest pivot) with
                                     // replacements (a stable factor stays near 1)
 // The panel's first sweep with G extra 64-row chunks in registers (rows
-// k0 + lane + 64 (1 + g)); P0 holds chunk 0 (the diagonal block) on return
-// and iv the signed pivot inverses, for the replay of any further chunks.
-// The multipliers of column jj are read from ps = a[.][jj] / L[jj][jj],
-// which equals L[.][jj] sg_jj exactly (the sign is folded into the
-// broadcast source instead of into every multiplier).
+// k0 + lane + 64 (1 + g)); gact (uniform) counts those that hold rows of
+// the system, and without any (gact = 0: chunks entirely past row N-1 would
+// only carry zeros) a scalar branch per column skips their updates.  P0 holds chunk 0 (the diagonal
+// block) on return and iv the signed pivot inverses, for the replay of any
+// further chunks.  The multipliers of column jj are read from
+// ps = a[.][jj] / L[jj][jj], which equals L[.][jj] sg_jj exactly (the sign
+// is folded into the broadcast source instead of into every multiplier).
 template <int G, class MF>
-QPD bool panel_sweep(MF *M, int N, int npos, int k0, int kb, bool dyn, float &pmax, int &nreg,
-                     float &lmax, float (&P0)[kNB], float (&iv)[kNB]) {
+QPD bool panel_sweep(MF *M, int N, int npos, int k0, int kb, int gact, bool dyn, float &pmax,
+                     int &nreg, float &lmax, float (&P0)[kNB], float (&iv)[kNB]) {
   const int lane = threadIdx.x & 63;
   float P[G > 0 ? G : 1][kNB];
   panel_load(M, N, k0, k0 + lane, P0);
@@ -578,35 +580,43 @@ QPD bool panel_sweep(MF *M, int N, int npos, int k0, int kb, bool dyn, float &pm
       iv[jj] = inv;
       const float ps = P0[jj] * rs;  // L[k0+lane][k0+jj] sg below the diagonal
       P0[jj] = lane > jj ? ps * sg : (lane == jj ? d : P0[jj]);
+      if constexpr (G <= 1) {
+        // the multipliers first, into scalar registers, then the updates:
+        // the broadcasts issue back to back instead of each waiting on the
+        // last one's result
+        float lc[kNB];
 #pragma unroll
-      for (int g = 0; g < G; ++g) P[g][jj] *= inv;
+        for (int cc = jj + 1; cc < kNB; ++cc) lc[cc] = readlane(ps, cc);  // L[k0+cc][k0+jj] sg
 #pragma unroll
-      for (int cc = jj + 1; cc < kNB; ++cc) {
-        const float lc = readlane(ps, cc);  // L[k0+cc][k0+jj] sg
-        P0[cc] = fmaf(-P0[jj], lc, P0[cc]);
+        for (int cc = jj + 1; cc < kNB; ++cc) P0[cc] = fmaf(-P0[jj], lc[cc], P0[cc]);
+        if (G == 1 && gact > 0) {
+          P[0][jj] *= inv;
 #pragma unroll
-        for (int g = 0; g < G; ++g) P[g][cc] = fmaf(-P[g][jj], lc, P[g][cc]);
+          for (int cc = jj + 1; cc < kNB; ++cc) P[0][cc] = fmaf(-P[0][jj], lc[cc], P[0][cc]);
+        }
+      } else if (gact > 0) {
+        // more chunks: one multiplier at a time (fewer scalar registers live)
+#pragma unroll
+        for (int g = 0; g < G; ++g) P[g][jj] *= inv;
+#pragma unroll
+        for (int cc = jj + 1; cc < kNB; ++cc) {
+          const float lc = readlane(ps, cc);  // L[k0+cc][k0+jj] sg
+          P0[cc] = fmaf(-P0[jj], lc, P0[cc]);
+#pragma unroll
+          for (int g = 0; g < G; ++g) P[g][cc] = fmaf(-P[g][jj], lc, P[g][cc]);
+        }
+      } else {
+#pragma unroll
+        for (int cc = jj + 1; cc < kNB; ++cc) P0[cc] = fmaf(-P0[jj], readlane(ps, cc), P0[cc]);
       }
     }
   }
   panel_store(M, N, k0, k0 + lane, P0, lmax);
+  if (gact > 0) {
 #pragma unroll
-  for (int g = 0; g < G; ++g) panel_store(M, N, k0, k0 + lane + 64 * (1 + g), P[g], lmax);
-  return fail;
-}
-
-// The first sweep with as many extra chunks as hold rows of the system
-// (gact), from G down: chunks entirely past row N-1 would only carry zeros.
-template <int G, class MF>
-QPD bool panel_sweep_upto(int gact, MF *M, int N, int npos, int k0, int kb, bool dyn,
-                          float &pmax, int &nreg, float &lmax, float (&P0)[kNB],
-                          float (&iv)[kNB]) {
-  if constexpr (G == 0) {
-    return panel_sweep<0>(M, N, npos, k0, kb, dyn, pmax, nreg, lmax, P0, iv);
-  } else {
-    if (gact >= G) return panel_sweep<G>(M, N, npos, k0, kb, dyn, pmax, nreg, lmax, P0, iv);
-    return panel_sweep_upto<G - 1>(gact, M, N, npos, k0, kb, dyn, pmax, nreg, lmax, P0, iv);
+    for (int g = 0; g < G; ++g) panel_store(M, N, k0, k0 + lane + 64 * (1 + g), P[g], lmax);
   }
+  return fail;
 }
 
 // The panel factorisation (see above).
@@ -617,14 +627,9 @@ QPD bool factor_panel(MF *M, int N, int npos, int k0, bool dyn, float &pmax, int
   const int lane = threadIdx.x & 63;
   const int kb = min(kNB, N - k0);
   float P0[kNB], iv[kNB];
-  bool fail;
-  if constexpr (GRP <= 3) {
-    // extra chunks that hold rows of the system (uniform)
-    const int gact = min(GRP, (N - k0 - 1) >> 6);
-    fail = panel_sweep_upto<GRP>(gact, M, N, npos, k0, kb, dyn, pmax, nreg, lmax, P0, iv);
-  } else {
-    fail = panel_sweep<GRP>(M, N, npos, k0, kb, dyn, pmax, nreg, lmax, P0, iv);
-  }
+  // extra chunks that hold rows of the system (uniform)
+  const int gact = min(GRP, (N - k0 - 1) >> 6);
+  const bool fail = panel_sweep<GRP>(M, N, npos, k0, kb, gact, dyn, pmax, nreg, lmax, P0, iv);
   // rows past the first 64 (1 + GRP): replay the eliminations with the
   // finished diagonal block, GRP chunks at a time
   float P[GRP > 0 ? GRP : 1][kNB];
@@ -977,26 +982,73 @@ QPD void kkt_matvecs(const gf *Q, const gf *G, const gf *A, int n, int m, int p,
 
 // ---------------------------------------------------------------------------
 // The per-QP context: LDS views plus this QP's global problem data.
+//
+// The addresses of the views live in a small table in LDS (one per
+// workgroup, written once per QP), not in the context object: each use
+// reads its entry back (a broadcast LDS load, made uniform), so no address
+// stays live in registers from one phase to the next.  Kept live, the
+// fifty-odd addresses overflow the scalar register file and are spilled and
+// reloaded one by one at every phase entry.  Global addresses take two
+// words.
+enum CtxSlot {
+  CS_X, CS_Y, CS_Z, CS_S, CS_V, CS_Q, CS_H, CS_B, CS_E, CS_D, CS_C,
+  CS_RT, CS_RI, CS_RE, CS_RZ, CS_RS, CS_TGZ, CS_TAY,
+  CS_T0, CS_T1, CS_U0, CS_U1, CS_DV0, CS_DV1, CS_DINV, CS_PART, CS_RED,
+  CS_W0, CS_W1, CS_RR, CS_RD, CS_PAN, CS_DD, CS_ROLE, CS_BIDX, CS_ELIST, CS_IFLAG, CS_STG,
+  CS_M = 40, CS_MZ = 42, CS_GQ = 44, CS_GQV = 46, CS_GA = 48, CS_GB = 50, CS_GG = 52,
+  CS_GH = 54, CS_N = 56
+};
+static __shared__ unsigned qpk_ctab[CS_N];
+static_assert(CS_N * 4 + 16 * 8 <= kStaticLds, "static LDS bound of the launch planning");
+
+// A context address: reads entry K of the table (PT carries the address
+// space, 32-bit LDS or 64-bit global addresses).
+template <class PT, int K>
+struct CtxRef {
+  QPD PT *get() const {
+    if constexpr (sizeof(PT *) == 4) {
+      return (PT *)(uintptr_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)qpk_ctab[K]);
+    } else {
+      const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)qpk_ctab[K]);
+      const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)qpk_ctab[K + 1]);
+      return (PT *)(uintptr_t)(((uint64_t)hi << 32) | lo);
+    }
+  }
+  QPD operator PT *() const { return get(); }
+  // by one thread; a barrier must follow before any use
+  QPD void set(PT *a) const {
+    const uint64_t v = (uint64_t)(uintptr_t)a;
+    qpk_ctab[K] = (uint32_t)v;
+    if constexpr (sizeof(PT *) == 8) qpk_ctab[K + 1] = (uint32_t)(v >> 32);
+  }
+};
+
 template <class MF>
 struct Ctx {
   typedef MF MT;
-  Layout L;
   int n, m, p, kb;
-  const gf *Q, *q_g, *A, *b_g, *G, *h_g;
-  lf *sm;    // LDS arena
-  MF *M;     // factor storage (LDS or global)
-  int ld;
-  lf *x, *y, *z, *s, *v, *q, *h, *b;
-  lf *E, *D, *c;
-  lf *rt, *ri, *re, *rz, *rs;
-  lf *tGz, *tAy;
-  lf *t0, *t1, *u0, *u1, *dv0, *dv1, *dinv;
-  lf *part, *red;
-  lf *w0, *w1, *rr, *rd, *pan;
-  MF *mz;    // 16 zeros after M's last row (same address space as M)
-  ldd *dd;
-  li *role, *bidx, *elist, *iflag;
-  lf *stg;    // matrix-core assembly staging (aliases u0 .. dd)
+  CtxRef<const gf, CS_GQ> Q;
+  CtxRef<const gf, CS_GQV> q_g;
+  CtxRef<const gf, CS_GA> A;
+  CtxRef<const gf, CS_GB> b_g;
+  CtxRef<const gf, CS_GG> G;
+  CtxRef<const gf, CS_GH> h_g;
+  CtxRef<MF, CS_M> M;    // factor storage (LDS or global)
+  CtxRef<lf, CS_X> x; CtxRef<lf, CS_Y> y; CtxRef<lf, CS_Z> z; CtxRef<lf, CS_S> s;
+  CtxRef<lf, CS_V> v; CtxRef<lf, CS_Q> q; CtxRef<lf, CS_H> h; CtxRef<lf, CS_B> b;
+  CtxRef<lf, CS_E> E; CtxRef<lf, CS_D> D; CtxRef<lf, CS_C> c;
+  CtxRef<lf, CS_RT> rt; CtxRef<lf, CS_RI> ri; CtxRef<lf, CS_RE> re; CtxRef<lf, CS_RZ> rz;
+  CtxRef<lf, CS_RS> rs; CtxRef<lf, CS_TGZ> tGz; CtxRef<lf, CS_TAY> tAy;
+  CtxRef<lf, CS_T0> t0; CtxRef<lf, CS_T1> t1; CtxRef<lf, CS_U0> u0; CtxRef<lf, CS_U1> u1;
+  CtxRef<lf, CS_DV0> dv0; CtxRef<lf, CS_DV1> dv1; CtxRef<lf, CS_DINV> dinv;
+  CtxRef<lf, CS_PART> part; CtxRef<lf, CS_RED> red;
+  CtxRef<lf, CS_W0> w0; CtxRef<lf, CS_W1> w1; CtxRef<lf, CS_RR> rr; CtxRef<lf, CS_RD> rd;
+  CtxRef<lf, CS_PAN> pan;
+  CtxRef<MF, CS_MZ> mz;  // 16 zeros after M's last row (same address space as M)
+  CtxRef<ldd, CS_DD> dd;
+  CtxRef<li, CS_ROLE> role; CtxRef<li, CS_BIDX> bidx; CtxRef<li, CS_ELIST> elist;
+  CtxRef<li, CS_IFLAG> iflag;
+  CtxRef<lf, CS_STG> stg;  // matrix-core assembly staging (aliases u0 .. dd)
   int amode;  // H-block assembly: 0 FP32 VALU, 1 BF16x3 MFMA, 2 FP32 MFMA
   int dyn;    // bounded form: regularise degenerate factorisations (R13)
   int rmode;  // residual precision: 0 FP32 first (FP64 refinement after a
@@ -1005,28 +1057,33 @@ struct Ctx {
   __attribute__((address_space(3))) long long *pt;
 };
 
+// Sizes and scalar settings of the context, and (thread 0) the address
+// table; the caller's next barrier publishes the table.
 template <class MF>
-QPD void init_ctx(Ctx<MF> &C, lf *sm, const Layout &L, MF *Mptr) {
-  C.L = L; C.n = L.n; C.m = L.m; C.p = L.p; C.kb = L.kb;
-  C.sm = sm;
-  C.M = Mptr;
-  C.ld = L.ld;
-  C.x = sm + L.x; C.y = sm + L.y; C.z = sm + L.z; C.s = sm + L.s; C.v = sm + L.v;
-  C.q = sm + L.q; C.h = sm + L.h; C.b = sm + L.b;
-  C.E = sm + L.E; C.D = sm + L.D; C.c = sm + L.c;
-  C.rt = sm + L.rt; C.ri = sm + L.ri; C.re = sm + L.re; C.rz = sm + L.rz; C.rs = sm + L.rs;
-  C.tGz = sm + L.tGz; C.tAy = sm + L.tAy;
-  C.t0 = sm + L.t0; C.t1 = sm + L.t1; C.u0 = sm + L.u0; C.u1 = sm + L.u1;
-  C.dv0 = sm + L.dv0; C.dv1 = sm + L.dv1; C.dinv = sm + L.dinv;
-  C.part = sm + L.part; C.red = sm + L.red;
-  C.w0 = sm + L.w0; C.w1 = sm + L.w1; C.rr = sm + L.rr; C.rd = sm + L.rd; C.pan = sm + L.pan;
-  C.mz = Mptr + moff(L.Nmax);
-  C.dd = reinterpret_cast<ldd *>(sm + L.dd);
-  C.role = reinterpret_cast<li *>(sm + L.role);
-  C.bidx = reinterpret_cast<li *>(sm + L.bidx);
-  C.elist = reinterpret_cast<li *>(sm + L.elist);
-  C.iflag = reinterpret_cast<li *>(sm + L.iflag);
-  C.stg = sm + L.stg;
+QPD void init_ctx(Ctx<MF> &C, lf *sm, const Layout &L, MF *Mptr, const gf *Qg, const gf *qg,
+                  const gf *Ag, const gf *bg, const gf *Gg, const gf *hg) {
+  C.n = L.n; C.m = L.m; C.p = L.p; C.kb = L.kb;
+  if (threadIdx.x == 0) {
+    C.Q.set(Qg); C.q_g.set(qg); C.A.set(Ag); C.b_g.set(bg); C.G.set(Gg); C.h_g.set(hg);
+    C.M.set(Mptr);
+    C.x.set(sm + L.x); C.y.set(sm + L.y); C.z.set(sm + L.z); C.s.set(sm + L.s);
+    C.v.set(sm + L.v); C.q.set(sm + L.q); C.h.set(sm + L.h); C.b.set(sm + L.b);
+    C.E.set(sm + L.E); C.D.set(sm + L.D); C.c.set(sm + L.c);
+    C.rt.set(sm + L.rt); C.ri.set(sm + L.ri); C.re.set(sm + L.re); C.rz.set(sm + L.rz);
+    C.rs.set(sm + L.rs); C.tGz.set(sm + L.tGz); C.tAy.set(sm + L.tAy);
+    C.t0.set(sm + L.t0); C.t1.set(sm + L.t1); C.u0.set(sm + L.u0); C.u1.set(sm + L.u1);
+    C.dv0.set(sm + L.dv0); C.dv1.set(sm + L.dv1); C.dinv.set(sm + L.dinv);
+    C.part.set(sm + L.part); C.red.set(sm + L.red);
+    C.w0.set(sm + L.w0); C.w1.set(sm + L.w1); C.rr.set(sm + L.rr); C.rd.set(sm + L.rd);
+    C.pan.set(sm + L.pan);
+    C.mz.set(Mptr + moff(L.Nmax));
+    C.dd.set(reinterpret_cast<ldd *>(sm + L.dd));
+    C.role.set(reinterpret_cast<li *>(sm + L.role));
+    C.bidx.set(reinterpret_cast<li *>(sm + L.bidx));
+    C.elist.set(reinterpret_cast<li *>(sm + L.elist));
+    C.iflag.set(reinterpret_cast<li *>(sm + L.iflag));
+    C.stg.set(sm + L.stg);
+  }
   C.amode = 0;
   C.dyn = 1;
   C.rmode = 0;
@@ -1035,28 +1092,13 @@ QPD void init_ctx(Ctx<MF> &C, lf *sm, const Layout &L, MF *Mptr) {
 }
 
 
-// Uniform copy of a context (see rfl).
+// Uniform copy of a context (see rfl): the sizes and settings; the
+// addresses are read from the table where they are used.
 template <class MF>
 QPD Ctx<MF> uctx(const Ctx<MF> &I) {
   Ctx<MF> C;
-  C.L = I.L;
-  C.n = rfl(I.n); C.m = rfl(I.m); C.p = rfl(I.p); C.kb = rfl(I.kb); C.ld = rfl(I.ld);
-  C.Q = rflp(I.Q); C.q_g = rflp(I.q_g); C.A = rflp(I.A); C.b_g = rflp(I.b_g);
-  C.G = rflp(I.G); C.h_g = rflp(I.h_g);
-  C.sm = rflp(I.sm); C.M = rflp(I.M);
-  C.x = rflp(I.x); C.y = rflp(I.y); C.z = rflp(I.z); C.s = rflp(I.s); C.v = rflp(I.v);
-  C.q = rflp(I.q); C.h = rflp(I.h); C.b = rflp(I.b);
-  C.E = rflp(I.E); C.D = rflp(I.D); C.c = rflp(I.c);
-  C.rt = rflp(I.rt); C.ri = rflp(I.ri); C.re = rflp(I.re); C.rz = rflp(I.rz); C.rs = rflp(I.rs);
-  C.tGz = rflp(I.tGz); C.tAy = rflp(I.tAy);
-  C.t0 = rflp(I.t0); C.t1 = rflp(I.t1); C.u0 = rflp(I.u0); C.u1 = rflp(I.u1);
-  C.dv0 = rflp(I.dv0); C.dv1 = rflp(I.dv1); C.dinv = rflp(I.dinv);
-  C.part = rflp(I.part); C.red = rflp(I.red);
-  C.w0 = rflp(I.w0); C.w1 = rflp(I.w1); C.rr = rflp(I.rr); C.rd = rflp(I.rd); C.pan = rflp(I.pan);
-  C.mz = rflp(I.mz);
-  C.dd = rflp(I.dd);
-  C.role = rflp(I.role); C.bidx = rflp(I.bidx); C.elist = rflp(I.elist); C.iflag = rflp(I.iflag);
-  C.stg = rflp(I.stg); C.amode = rfl(I.amode); C.dyn = rfl(I.dyn); C.rmode = rfl(I.rmode); C.bo = rflf(I.bo);
+  C.n = rfl(I.n); C.m = rfl(I.m); C.p = rfl(I.p); C.kb = rfl(I.kb);
+  C.amode = rfl(I.amode); C.dyn = rfl(I.dyn); C.rmode = rfl(I.rmode); C.bo = rflf(I.bo);
   C.pt = rflp(I.pt);
   return C;
 }
@@ -1078,8 +1120,8 @@ QPK_PHASE float residuals(CT &Cin_, bool bounded, float kappa, float kr, bool *b
   const int n = C.n, m = C.m, p = C.p, tid = threadIdx.x;
   // one accumulator for Qx + G'z + A'y; the pieces' norms are taken as they
   // are produced
-  la *gxd = reinterpret_cast<la *>(C.dd), *axd = gxd + m, *rtd = gxd + m + p;
-  la *pd = reinterpret_cast<la *>(C.part);
+  la *gxd = reinterpret_cast<la *>(C.dd.get()), *axd = gxd + m, *rtd = gxd + m + p;
+  la *pd = reinterpret_cast<la *>(C.part.get());
   enum { RT, QX, QQ, GZ, AY, RI, GX, SS, HH, RE, AX, BB, RZS, ZZ, CC, NF, NK };
   float mx[NK];
 #pragma unroll
@@ -1174,7 +1216,7 @@ QPK_PHASE int partition_bounded(CT &Cin_, float kappa) {
   kappa = rflf(kappa);
   const int m = C.m, kb = C.kb, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   constexpr int NW = T / 64;
-  li *ws = reinterpret_cast<li *>(C.red);  // per-wave counts [2][NW]
+  li *ws = reinterpret_cast<li *>(C.red.get());  // per-wave counts [2][NW]
   const unsigned long long below = (1ull << lane) - 1ull;
   // One sweep: retraction derivatives, and the border / eliminated lists in
   // row order from wave ballots (the common case: at most kb rows with v > 0)
@@ -1226,7 +1268,7 @@ QPK_PHASE int partition_bounded(CT &Cin_, float kappa) {
     // ahead of it; v is read four rows per 16-byte broadcast load, several
     // loads in flight, and the padding past row m is masked.
     li *cand = C.role;
-    const lf4 *v4 = reinterpret_cast<const lf4 *>(C.v);
+    const lf4 *v4 = reinterpret_cast<const lf4 *>(C.v.get());
     const int m4 = (m + 3) >> 2;
     for (int i = tid; i < m; i += T) {
       int f = 0;
@@ -1307,7 +1349,7 @@ QPD void assemble_h_mfma(CT &C, int ne, const lf *wts) {
   const bool bf = C.amode == 1;
   const int g = lane >> 4, c16 = lane & 15;
   lf *stg = C.stg;
-  auto *M = C.M;
+  auto *M = C.M.get();
   for (int pass = 0; pass < passes; ++pass) {
     int ti[kAsmTiles], tj[kAsmTiles];
     bool val[kAsmTiles];
@@ -1401,7 +1443,7 @@ QPK_PHASE void assemble(CT &Cin_, int nb, int ne, const lf *wts, bool bounded, f
   CT C = uctx(Cin_);
   nb = rfl(nb); ne = rfl(ne); wts = rflp(wts); bounded = rfl(bounded); delta = rflf(delta);
   const int n = C.n, p = C.p, tid = threadIdx.x;
-  auto *M = C.M;
+  auto *M = C.M.get();
   if (C.amode != 0) {
     assemble_h_mfma<T>(C, ne, wts);
   } else {
@@ -1549,11 +1591,11 @@ QPK_PHASE void solve2(CT &Cin_, int N, bool both) {
   N = rfl(N); both = rfl(both);
   const int wid = threadIdx.x >> 6;
   if constexpr (T >= 128) {
-    if (wid == 0) signed_solve_wave<RPL>(C.M, N, C.n, C.dinv, C.u0, C.mz);
-    else if (wid == 1 && both) signed_solve_wave<RPL>(C.M, N, C.n, C.dinv, C.u1, C.mz);
+    if (wid == 0) signed_solve_wave<RPL>(C.M.get(), N, C.n, C.dinv, C.u0, C.mz.get());
+    else if (wid == 1 && both) signed_solve_wave<RPL>(C.M.get(), N, C.n, C.dinv, C.u1, C.mz.get());
   } else {
-    signed_solve_wave<RPL>(C.M, N, C.n, C.dinv, C.u0, C.mz);
-    if (both) signed_solve_wave<RPL>(C.M, N, C.n, C.dinv, C.u1, C.mz);
+    signed_solve_wave<RPL>(C.M.get(), N, C.n, C.dinv, C.u0, C.mz.get());
+    if (both) signed_solve_wave<RPL>(C.M.get(), N, C.n, C.dinv, C.u1, C.mz.get());
   }
   __syncthreads();
 }
@@ -1582,8 +1624,8 @@ template <int T, class AT, class CT>
 QPD void kkt_apply(CT &C, int nb, bool bounded, const lf *w, const lf *u, lf *out, bool sub) {
   typedef typename LdsT<AT>::type la;
   const int n = C.n, m = C.m, p = C.p, tid = threadIdx.x;
-  la *gx = reinterpret_cast<la *>(C.dd), *ax = gx + m, *phi = gx + m + p, *kx = gx + 2 * m + p;
-  la *pd = reinterpret_cast<la *>(C.part);
+  la *gx = reinterpret_cast<la *>(C.dd.get()), *ax = gx + m, *phi = gx + m + p, *kx = gx + 2 * m + p;
+  la *pd = reinterpret_cast<la *>(C.part.get());
   // G u, A u and Q'u_x + A'u_y in one pass; then G' phi, which needs G u
   float unused[3];
   kkt_matvecs<T, AT>(C.Q, C.G, C.A, n, m, p, u, u, false, u + n + nb, gx, ax, kx, pd, unused[0],
@@ -1594,7 +1636,7 @@ QPD void kkt_apply(CT &C, int nb, bool bounded, const lf *w, const lf *u, lf *ou
     phi[i] = k >= 0 ? (AT)u[n + k] : wi * gx[i];
   }
   __syncthreads();
-  if (m) coldot_d<T, AT>(C.G, n, m, n, phi, kx, true, pd);
+  if (m) coldot_d<T, AT>(C.G.get(), n, m, n, phi, kx, true, pd);
   const AT sg = sub ? (AT)-1 : (AT)1;
   for (int j = tid; j < n; j += T) out[j] = (float)((sub ? (AT)w[j] : (AT)0) + sg * kx[j]);
   for (int k = tid; k < nb; k += T) {
@@ -1660,7 +1702,7 @@ QPK_PHASE float refine(CT &Cin_, int nb, bool bounded, const lf *w, lf *u, int s
     }
     if (it == steps) break;
     prev = nrm;
-    if (threadIdx.x < 64) signed_solve_wave<RPL>(C.M, N, n, C.dinv, r, C.mz);
+    if (threadIdx.x < 64) signed_solve_wave<RPL>(C.M.get(), N, n, C.dinv, r, C.mz.get());
     __syncthreads();
     for (int j = tid; j < N; j += T) {
       C.rd[j] = r[j];
@@ -1759,7 +1801,7 @@ QPD bool factor_bounded(CT &C, int nb, int ne, const lf *wts, float delta_rel, b
     border_delta<T>(C, nb, delta_rel, 0.f);
   }
   QPK_PT(C, PH_ASM);
-  bool ok = signed_cholesky<T, RPL>(C.M, N, C.n, C.iflag, C.dyn != 0);
+  bool ok = signed_cholesky<T, RPL>(C.M.get(), N, C.n, C.iflag, C.dyn != 0);
   QPK_PT(C, PH_FACT);
   *regularised = delta_rel > 0.f || floor || C.iflag[2] > 0;
   if (!ok && C.dyn) {
@@ -1768,7 +1810,7 @@ QPD bool factor_bounded(CT &C, int nb, int ne, const lf *wts, float delta_rel, b
     const float pmax = __int_as_float(C.iflag[4]);
     assemble<T>(C, nb, ne, wts, true, 0.f);
     border_delta<T>(C, nb, fmaxf(delta_rel, 1e-6f), kRetryReg * pmax);
-    ok = signed_cholesky<T, RPL>(C.M, N, C.n, C.iflag, true);
+    ok = signed_cholesky<T, RPL>(C.M.get(), N, C.n, C.iflag, true);
     *regularised = true;
   }
   return ok;
@@ -1816,11 +1858,11 @@ QPK_PHASE void rhs_bounded(CT &Cin_, int nb, float kappa, const gf *gx, const gf
     if (!adj) {
       const lf *xv[2] = {C.t0, C.t1};
       lf *o[2] = {C.tGz, C.tAy};
-      coldot<T, 2>(C.G, n, m, n, xv, o, C.part);
+      coldot<T, 2>(C.G.get(), n, m, n, xv, o, C.part);
     } else {
       const lf *xv[1] = {C.t0};
       lf *o[1] = {C.tGz};
-      coldot<T, 1>(C.G, n, m, n, xv, o, C.part);
+      coldot<T, 1>(C.G.get(), n, m, n, xv, o, C.part);
     }
   }
   for (int i = tid; i < n; i += T) {
@@ -1855,11 +1897,11 @@ QPK_PHASE void recover_bounded(CT &Cin_, int nb, bool both) {
   if (both) {
     const lf *xv[2] = {C.u0, C.u1};
     lf *o[2] = {C.t0, C.t1};
-    rowdot<T, 2>(C.G, n, m, n, xv, o);
+    rowdot<T, 2>(C.G.get(), n, m, n, xv, o);
   } else {
     const lf *xv[1] = {C.u0};
     lf *o[1] = {C.t0};
-    rowdot<T, 1>(C.G, n, m, n, xv, o);
+    rowdot<T, 1>(C.G.get(), n, m, n, xv, o);
   }
   __syncthreads();
   for (int i = tid; i < m; i += T) {
@@ -1909,12 +1951,12 @@ QPK_PHASE bool initialize(CT &Cin_, double &work, bool dyn) {
   const int ne = compact_rows<T>(C.role, m, C.elist, C.red);
   assemble<T>(C, 0, ne, C.E, false, 0.f);
   const int N = n + p;
-  const bool ok = signed_cholesky<T, RPL>(C.M, N, n, C.iflag, dyn);
+  const bool ok = signed_cholesky<T, RPL>(C.M.get(), N, n, C.iflag, dyn);
   make_dinv<T>(C, N);
   if (m) {
     const lf *hv[1] = {C.h};
     lf *o[1] = {C.tGz};
-    coldot<T, 1>(C.G, n, m, n, hv, o, C.part);
+    coldot<T, 1>(C.G.get(), n, m, n, hv, o, C.part);
   }
   for (int i = tid; i < n; i += T) C.u0[i] = C.w0[i] = -C.q[i] + (m ? C.tGz[i] : 0.f);
   for (int k = tid; k < p; k += T) C.u0[n + k] = C.w0[n + k] = C.b[k];
@@ -1930,7 +1972,7 @@ QPK_PHASE bool initialize(CT &Cin_, double &work, bool dyn) {
   if (m) {
     const lf *xv[1] = {C.x};
     lf *o[1] = {C.t0};
-    rowdot<T, 1>(C.G, n, m, n, xv, o);
+    rowdot<T, 1>(C.G.get(), n, m, n, xv, o);
     __syncthreads();
     float mx[2] = {-kBig, -kBig};
     for (int i = tid; i < m; i += T) {
@@ -2105,7 +2147,7 @@ QPK_PHASE int newton_standard(CT &Cin_, float mu, int kt_mode, float kr, float d
   __syncthreads();
   const int N = n + p;
   assemble<T>(C, 0, ne, C.E, false, delta_reg);
-  const bool ok = signed_cholesky<T, RPL>(C.M, N, n, C.iflag, false);
+  const bool ok = signed_cholesky<T, RPL>(C.M.get(), N, n, C.iflag, false);
   const double dn = n, dm = m, dp = p, dN = N;
   work += 2.0 * dn * dn + 4.0 * dm * dn + 4.0 * dp * dn;
   work += dm * dn * (dn + 1.0) + dN * dN * dN / 3.0;
@@ -2120,7 +2162,7 @@ QPK_PHASE int newton_standard(CT &Cin_, float mu, int kt_mode, float kr, float d
     {
       const lf *xv[1] = {C.t0};
       lf *o[1] = {C.tGz};
-      if (m) coldot<T, 1>(C.G, n, m, n, xv, o, C.part);
+      if (m) coldot<T, 1>(C.G.get(), n, m, n, xv, o, C.part);
     }
     for (int i = tid; i < n; i += T) C.u0[i] = -C.rt[i] - (m ? C.tGz[i] : 0.f);
     for (int k = tid; k < p; k += T) C.u0[n + k] = -C.re[k];
@@ -2128,7 +2170,7 @@ QPK_PHASE int newton_standard(CT &Cin_, float mu, int kt_mode, float kr, float d
     solve2<T, RPL>(C, N, false);
     const lf *xv[1] = {C.u0};
     lf *o[1] = {C.t0};
-    if (m) rowdot<T, 1>(C.G, n, m, n, xv, o);
+    if (m) rowdot<T, 1>(C.G.get(), n, m, n, xv, o);
     __syncthreads();
   };
   float sgm;
@@ -2385,7 +2427,7 @@ QPK_PHASE int adjoint(CT &Cin_, bool bounded, const gf *gx, const gf *gy, const 
     for (int i = tid; i < m; i += T) C.dv0[i] = C.E[i] * (C.dv0[i] + (gz ? gz[i] : 0.f));
   } else {
     assemble<T>(C, nb, ne, C.t1, false, 0.f);
-    ok = signed_cholesky<T, RPL>(C.M, N, n, C.iflag, false);
+    ok = signed_cholesky<T, RPL>(C.M.get(), N, n, C.iflag, false);
     const int nref = plain_refine_steps(C.rmode, refine_steps, 2);
     work += wfac + nref * wstep;
     if (!ok) return kAdjFactorFail;
@@ -2396,7 +2438,7 @@ QPK_PHASE int adjoint(CT &Cin_, bool bounded, const gf *gx, const gf *gy, const 
     if (m) {
       const lf *xv[1] = {C.t0};
       lf *o[1] = {C.tGz};
-      coldot<T, 1>(C.G, n, m, n, xv, o, C.part);
+      coldot<T, 1>(C.G.get(), n, m, n, xv, o, C.part);
     }
     for (int i = tid; i < n; i += T) C.u0[i] = C.w0[i] = -gx[i] - (m ? C.tGz[i] : 0.f);
     for (int k = tid; k < p; k += T) C.u0[n + k] = C.w0[n + k] = gy ? -gy[k] : 0.f;
@@ -2410,7 +2452,7 @@ QPK_PHASE int adjoint(CT &Cin_, bool bounded, const gf *gx, const gf *gy, const 
     if (m) {
       const lf *xv[1] = {C.u0};
       lf *o[1] = {C.t0};
-      rowdot<T, 1>(C.G, n, m, n, xv, o);
+      rowdot<T, 1>(C.G.get(), n, m, n, xv, o);
     }
     __syncthreads();
     for (int i = tid; i < m; i += T) C.dv0[i] = C.E[i] * (C.t0[i] + (gz ? gz[i] : 0.f));
@@ -2510,13 +2552,9 @@ QPD void qp_body(const Params &P) {
   if constexpr (MLDS) Mp = sm + L.M;
   else Mp = (gf *)wsp;
   Ctx<MF> C;
-  init_ctx(C, sm, L, Mp);
-  C.Q = (const gf *)Qp;
-  C.q_g = (const gf *)qp;
-  C.A = (const gf *)Ap;
-  C.b_g = (const gf *)bp;
-  C.G = (const gf *)Gp;
-  C.h_g = (const gf *)hp;
+  init_ctx(C, sm, L, Mp, (const gf *)Qp, (const gf *)qp, (const gf *)Ap, (const gf *)bp,
+           (const gf *)Gp, (const gf *)hp);
+  __syncthreads();  // the context table
   if constexpr (MODE == kServe) C.amode = (P.desc[qi].flags >> 1) & 3;
   else C.amode = P.asm_mode;
   const int amode0 = C.amode;

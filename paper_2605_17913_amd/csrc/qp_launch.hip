@@ -13,7 +13,7 @@ int64_t ws_floats(int n, int m, int p, int kb) {
   return (int64_t)al4(moff(L.Nmax) + kNB);
 }
 
-size_t lds_limit() { return 160 * 1024; }
+size_t lds_limit() { return kCuLds - kStaticLds; }
 
 bool mfma_stage_fits(int n, int m, int p, int kb, bool m_in_lds, int threads) {
   const Layout L = make_layout(n, m, p, kb, m_in_lds, threads);
