@@ -123,12 +123,13 @@ inline int make_plan(int n, int m, int p, const qp_opts &o, Plan *pl) {
   const size_t lim = qpk::lds_limit();
   const size_t with_m = qpk::lds_bytes(n, m, p, kb, true, T);
   // QPs resident per CU: LDS-limited, and at most the waves the register
-  // allocation targets (three per SIMD up to 256 threads, two at 512).  A
+  // allocation targets (three per SIMD up to 256 threads, four at 256
+  // threads with more than 128 rows, two at 512).  A
   // factor that fits LDS but halves (or worse) the residency of the
   // global-factor layout goes to global memory instead: at n = 100 the LDS
   // factor leaves one QP per CU, the global one three (15% faster).
   const size_t cu_lds = qpk::kCuLds;
-  const int cu_waves = 4 * (T >= 512 ? 2 : 3);
+  const int cu_waves = 4 * (T >= 512 ? 2 : (T == 256 && N > 128 ? 4 : 3));
   auto per_cu = [&](size_t bytes) {
     return std::min<size_t>(cu_lds / (bytes + qpk::kStaticLds), cu_waves / (T / 64));
   };

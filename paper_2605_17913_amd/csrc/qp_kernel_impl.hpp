@@ -589,7 +589,7 @@ QPD bool panel_sweep(MF *M, int N, int npos, int k0, int kb, int gact, bool dyn,
         for (int cc = jj + 1; cc < kNB; ++cc) lc[cc] = readlane(ps, cc);  // L[k0+cc][k0+jj] sg
 #pragma unroll
         for (int cc = jj + 1; cc < kNB; ++cc) P0[cc] = fmaf(-P0[jj], lc[cc], P0[cc]);
-        if (G == 1 && gact > 0) {
+        if (G == 1) {  // (zeros past row N-1: a branch on gact costs more)
           P[0][jj] *= inv;
 #pragma unroll
           for (int cc = jj + 1; cc < kNB; ++cc) P[0][cc] = fmaf(-P[0][jj], lc[cc], P[0][cc]);
@@ -2706,26 +2706,33 @@ QPD void qp_body(const Params &P) {
 }
 
 // Waves per SIMD the register allocation targets: 3 (168 VGPRs) up to 256
-// threads per QP, 2 (256 VGPRs) at 512.  At 128 threads, 4 waves (128 VGPRs)
-// spilled about twice as much and ran 24% slower on n = 10 and n = 20.
-#define QPK_MIN_WAVES(T) ((T) >= 512 ? 2 : 3)
+// threads per QP, 2 (256 VGPRs) at 512, and 4 (128 VGPRs) for 256 threads
+// with 4 rows per lane in the solve and serving kernels, whose systems (129
+// to 256 rows) keep the factor in global memory with a small LDS footprint,
+// so four QPs fit a CU (n = 100: solve 13.6 -> 12.5 ms; the backward kernel
+// at four waves spilled into a 25% slower launch and keeps three).  At 128
+// threads, 4 waves spilled about twice as much and ran 24% slower on n = 10
+// and n = 20; the n = 50 kernel (2 rows per lane) is held to three QPs per
+// CU by LDS.
+#define QPK_MIN_WAVES(T, RPL) ((T) >= 512 ? 2 : ((T) == 256 && (RPL) == 4 ? 4 : 3))
+#define QPK_MIN_WAVES_BWD(T) ((T) >= 512 ? 2 : 3)
 
 // One workgroup per QP: Algorithm 1 (or the standard IPM) end to end.
 template <int T, int RPL, bool MLDS>
-__global__ void __launch_bounds__(T, QPK_MIN_WAVES(T)) qp_solve_kernel(Params P) {
+__global__ void __launch_bounds__(T, QPK_MIN_WAVES(T, RPL)) qp_solve_kernel(Params P) {
   qp_body<T, RPL, MLDS, kSolve>(P);
 }
 
 // One workgroup per QP: relax (Algorithm 2), adjoint solve and parameter
 // gradients (Algorithm 3).
 template <int T, int RPL, bool MLDS>
-__global__ void __launch_bounds__(T, QPK_MIN_WAVES(T)) qp_backward_kernel(Params P) {
+__global__ void __launch_bounds__(T, QPK_MIN_WAVES_BWD(T)) qp_backward_kernel(Params P) {
   qp_body<T, RPL, MLDS, kBackward>(P);
 }
 
 // One workgroup per resident serving slot: resume its Newton loop.
 template <int T, int RPL, bool MLDS>
-__global__ void __launch_bounds__(T, QPK_MIN_WAVES(T)) qp_serve_kernel(Params P) {
+__global__ void __launch_bounds__(T, QPK_MIN_WAVES(T, RPL)) qp_serve_kernel(Params P) {
   qp_body<T, RPL, MLDS, kServe>(P);
 }
 
