@@ -124,18 +124,19 @@ inline int make_plan(int n, int m, int p, const qp_opts &o, Plan *pl) {
   const size_t with_m = qpk::lds_bytes(n, m, p, kb, true, T);
   // QPs resident per CU: LDS-limited, and at most the waves the register
   // allocation targets (three per SIMD up to 256 threads, four at 256
-  // threads with more than 128 rows, two at 512).  A
+  // threads with more than 128 rows and the factor in global memory, two at
+  // 512).  A
   // factor that fits LDS but halves (or worse) the residency of the
   // global-factor layout goes to global memory instead: at n = 100 the LDS
   // factor leaves one QP per CU, the global one three (15% faster).
   const size_t cu_lds = qpk::kCuLds;
-  const int cu_waves = 4 * (T >= 512 ? 2 : (T == 256 && N > 128 ? 4 : 3));
-  auto per_cu = [&](size_t bytes) {
+  auto per_cu = [&](size_t bytes, bool global) {
+    const int cu_waves = 4 * (T >= 512 ? 2 : (T == 256 && N > 128 && global ? 4 : 3));
     return std::min<size_t>(cu_lds / (bytes + qpk::kStaticLds), cu_waves / (T / 64));
   };
   const bool fits = with_m <= lim;
   const bool prefer_global =
-      fits && per_cu(qpk::lds_bytes(n, m, p, kb, false, T)) >= 2 * per_cu(with_m);
+      fits && per_cu(qpk::lds_bytes(n, m, p, kb, false, T), true) >= 2 * per_cu(with_m, false);
   if (fits && !prefer_global) {
     pl->m_in_lds = true;
     pl->lds = with_m;

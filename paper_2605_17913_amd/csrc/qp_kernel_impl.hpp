@@ -2707,19 +2707,20 @@ QPD void qp_body(const Params &P) {
 
 // Waves per SIMD the register allocation targets: 3 (168 VGPRs) up to 256
 // threads per QP, 2 (256 VGPRs) at 512, and 4 (128 VGPRs) for 256 threads
-// with 4 rows per lane in the solve and serving kernels, whose systems (129
-// to 256 rows) keep the factor in global memory with a small LDS footprint,
-// so four QPs fit a CU (n = 100: solve 13.6 -> 12.5 ms; the backward kernel
-// at four waves spilled into a 25% slower launch and keeps three).  At 128
-// threads, 4 waves spilled about twice as much and ran 24% slower on n = 10
-// and n = 20; the n = 50 kernel (2 rows per lane) is held to three QPs per
-// CU by LDS.
-#define QPK_MIN_WAVES(T, RPL) ((T) >= 512 ? 2 : ((T) == 256 && (RPL) == 4 ? 4 : 3))
+// with 4 rows per lane and the factor in global memory in the solve and
+// serving kernels: their systems (129 to 256 rows) leave a small LDS
+// footprint, so four QPs fit a CU (n = 100: solve 13.6 -> 12.5 ms; the
+// backward kernel at four waves spilled into a 25% slower launch and keeps
+// three).  At 128 threads, 4 waves spilled about twice as much and ran 24%
+// slower on n = 10 and n = 20; kernels with the factor in LDS are held to
+// three QPs per CU or fewer by LDS.
+#define QPK_MIN_WAVES(T, RPL, MLDS) \
+  ((T) >= 512 ? 2 : ((T) == 256 && (RPL) == 4 && !(MLDS) ? 4 : 3))
 #define QPK_MIN_WAVES_BWD(T) ((T) >= 512 ? 2 : 3)
 
 // One workgroup per QP: Algorithm 1 (or the standard IPM) end to end.
 template <int T, int RPL, bool MLDS>
-__global__ void __launch_bounds__(T, QPK_MIN_WAVES(T, RPL)) qp_solve_kernel(Params P) {
+__global__ void __launch_bounds__(T, QPK_MIN_WAVES(T, RPL, MLDS)) qp_solve_kernel(Params P) {
   qp_body<T, RPL, MLDS, kSolve>(P);
 }
 
@@ -2732,7 +2733,7 @@ __global__ void __launch_bounds__(T, QPK_MIN_WAVES_BWD(T)) qp_backward_kernel(Pa
 
 // One workgroup per resident serving slot: resume its Newton loop.
 template <int T, int RPL, bool MLDS>
-__global__ void __launch_bounds__(T, QPK_MIN_WAVES(T, RPL)) qp_serve_kernel(Params P) {
+__global__ void __launch_bounds__(T, QPK_MIN_WAVES(T, RPL, MLDS)) qp_serve_kernel(Params P) {
   qp_body<T, RPL, MLDS, kServe>(P);
 }
 
