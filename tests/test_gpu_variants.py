@@ -1,0 +1,79 @@
+"""Every compiled kernel configuration against the FP64 oracle.
+
+The library instantiates its fused kernels per (threads per QP, rows per
+lane in the solves, factor in LDS or in global memory); the launch plan
+picks one from the problem size (and `block`, when given).  Each case below
+is the smallest random feasible shape whose plan lands on one of the 18
+reachable configurations (the plan is asserted, so the case keeps covering
+the configuration it names).  For QP 0 of each batch: the solution entry by
+entry (x, s, y, z), then the relaxed point and all six gradient blocks,
+with the tolerances of tests/parity.py.
+"""
+import numpy as np
+import pytest
+
+import qpgen
+from oracle import implicit, gradients
+
+import parity as pt
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+# (threads, rows per lane, factor in LDS) -> (n, m, p)
+CASES = {
+    (128, 1, True): (2, 1, 0),
+    (128, 2, True): (26, 26, 13),
+    (128, 2, False): (47, 47, 23),
+    (128, 4, True): (56, 896, 28),
+    (128, 4, False): (53, 53, 26),
+    (128, 8, False): (104, 104, 52),
+    (256, 1, True): (2, 1, 0),
+    (256, 2, True): (26, 26, 13),
+    (256, 2, False): (47, 500, 23),
+    (256, 4, True): (53, 53, 26),
+    (256, 4, False): (56, 56, 28),
+    (256, 8, False): (104, 104, 52),
+    (512, 1, True): (2, 1, 0),
+    (512, 2, True): (26, 26, 13),
+    (512, 4, True): (53, 53, 26),
+    (512, 4, False): (146, 37, 73),
+    (512, 8, False): (104, 104, 52),
+    (512, 16, False): (95, 380, 47),
+}
+KR = 1e-4
+
+
+def _rows_per_lane(N):
+    r = (N + 63) // 64
+    return 1 if r <= 1 else 2 if r <= 2 else 4 if r <= 4 else 8 if r <= 8 else 16
+
+
+@pytest.mark.parametrize("key", sorted(CASES), ids=lambda k: f"T{k[0]}_rpl{k[1]}_{'lds' if k[2] else 'global'}")
+def test_kernel_configuration_vs_oracle(key):
+    import paper_2605_17913_amd as qpx
+    T, rpl, lds = key
+    n, m, p = CASES[key]
+    pl = qpx.plan(n, m, p, block=T)
+    assert (pl["threads"], _rows_per_lane(n + pl["kb"] + p), pl["factor_in_lds"]) == key, pl
+    print(f"configuration {key}: n={n} m={m} p={p} B=3", flush=True)
+    P = qpgen.random_feasible(3, n, m, p, seed=100 + n + m + p)
+    Td = pt.to_dev(P)
+    sol = qpx.solve(*Td, block=T)
+    gx = qpgen.upstream(P.B, n, seed=7)
+    g = qpx.backward(*Td, sol, torch.from_numpy(gx).to(Td[0].device), kappa_relax=KR,
+                     relaxed=True, block=T)
+    torch.cuda.synchronize()
+    sol, g = pt.npd(sol), pt.npd(g)
+    st = pt.outcome(sol["status"])
+    assert np.all(st == 0), (key, st.tolist(), sol["iters"].tolist())
+    rst = pt.outcome(g["relaxed"]["status"])
+    assert np.all(rst == 0), (key, rst.tolist())
+    r = implicit.solve_qp(*P.one(0), tol=1e-11, max_iter=200)
+    assert r.status == implicit.CONVERGED
+    worst = pt.check_point(f"{key} QP 0", P, 0, sol, r)
+    ref, rr = gradients.grad_at_relaxed(*P.one(0), KR, gx[0].astype(np.float64))
+    worst = max(worst, pt.check_point(f"{key} relaxed QP 0", P, 0, g["relaxed"], rr, tol=1e-6))
+    worst = max(worst, pt.check_grads(f"{key} QP 0", g, 0, ref))
+    print(f"  iters {sol['iters'].tolist()} worst entry at {worst:.2f} of its bound", flush=True)
