@@ -2669,13 +2669,16 @@ QPD void qp_body(const Params &P) {
       C.s[i] = ss[qi * m + i];
     }
     __syncthreads();
-    // On QPs with more than four inequality rows per variable the
+    // On QPs with at least three inequality rows per variable the
     // relaxation refines its steps: H then sums that many rank-one terms in
     // FP32, and the relaxed multipliers, to which the gradients are
     // sensitive, drift by about 1e-5 relative (n = 56, m = 896, p = 28:
     // gradient entries off by up to 0.8% without; with one refinement step
-    // per relaxation step every entry is within 0.4% of its 1e-3 bound).
-    const int refine_relax = bounded && m > 4 * n ? max(refine, 1) : refine;
+    // per relaxation step every entry is within 0.4% of its 1e-3 bound;
+    // n = 200, m = 800 missed the bound by 2.6x without).  At m = 2n (the
+    // benchmark shapes) it would cost 44% of the backward pass for no
+    // measurable gain.
+    const int refine_relax = bounded && m >= 3 * n ? max(refine, 1) : refine;
     status = newton_loop<T, RPL>(C, bounded, P.relax_max_iter, P.relax_tol, 2, 0.f, P.kappa_relax,
                                  P.delta_reg, refine_relax, work, iters, res);
     // without inequalities there is nothing to relax: the relaxed point is
