@@ -531,7 +531,8 @@ QPD void panel_store(MF *M, int N, int k0, int i, const float (&R)[kNB], float &
 // Returns true if a pivot failed.
 //
 // Dynamic regularisation (dyn): a pivot sg*a_jj that is not above
-// kPivTol * pmax, with pmax the largest pivot accepted so far, is taken as
+// kPivTol * pmax, with pmax the largest pivot accepted so far in its block
+// (the H block, or the border from its first column on), is taken as
 // numerically zero (or of the wrong sign through rounding) and replaced by
 // kPivReg * pmax; nreg counts the replacements.  The factor is then that of
 // M plus a small diagonal, and callers refine against the exact operator.
@@ -551,7 +552,7 @@ constexpr float kGrowthMax = 1e2f;  // accepted max|L| / sqrt(largest pivot) wit
 // is folded into the broadcast source instead of into every multiplier).
 template <int G, class MF>
 QPD bool panel_sweep(MF *M, int N, int npos, int k0, int kb, int gact, bool dyn, float &pmax,
-                     int &nreg, float &lmax, float (&P0)[kNB], float (&iv)[kNB]) {
+                     float &pmaxh, int &nreg, float &lmax, float (&P0)[kNB], float (&iv)[kNB]) {
   const int lane = threadIdx.x & 63;
   float P[G > 0 ? G : 1][kNB];
   panel_load(M, N, k0, k0 + lane, P0);
@@ -564,6 +565,14 @@ QPD bool panel_sweep(MF *M, int N, int npos, int k0, int kb, int gact, bool dyn,
     if (jj < kb) {
       // row k0+jj is in lane jj of chunk 0
       const float sg = (k0 + jj) < npos ? 1.f : -1.f;
+      // the border's pivots (its Schur complement, of order |C_j|^2 / |H|
+      // plus the diagonal Dl) are tested against the border's own largest
+      // pivot: at the first border column the running maximum restarts
+      // (the H block's is kept in pmaxh)
+      if (k0 + jj == npos) {
+        pmaxh = pmax;
+        pmax = 0.f;
+      }
       float tt = sg * readlane(P0[jj], jj);
       if (dyn && !(tt > kPivTol * pmax) && tt >= -FLT_MAX && pmax > 0.f) {
         tt = kPivReg * pmax;
@@ -621,15 +630,16 @@ QPD bool panel_sweep(MF *M, int N, int npos, int k0, int kb, int gact, bool dyn,
 
 // The panel factorisation (see above).
 template <int RPL, class MF>
-QPD bool factor_panel(MF *M, int N, int npos, int k0, bool dyn, float &pmax, int &nreg,
-                      float &lmax) {
+QPD bool factor_panel(MF *M, int N, int npos, int k0, bool dyn, float &pmax, float &pmaxh,
+                      int &nreg, float &lmax) {
   constexpr int GRP = RPL - 1 < 4 ? RPL - 1 : 4;
   const int lane = threadIdx.x & 63;
   const int kb = min(kNB, N - k0);
   float P0[kNB], iv[kNB];
   // extra chunks that hold rows of the system (uniform)
   const int gact = min(GRP, (N - k0 - 1) >> 6);
-  const bool fail = panel_sweep<GRP>(M, N, npos, k0, kb, gact, dyn, pmax, nreg, lmax, P0, iv);
+  const bool fail =
+      panel_sweep<GRP>(M, N, npos, k0, kb, gact, dyn, pmax, pmaxh, nreg, lmax, P0, iv);
   // rows past the first 64 (1 + GRP): replay the eliminations with the
   // finished diagonal block, GRP chunks at a time
   float P[GRP > 0 ? GRP : 1][kNB];
@@ -675,11 +685,11 @@ QPK_PHASE bool signed_cholesky(MF *M, int N, int npos, li *flag, bool dyn) {
   M = rflp(M); N = rfl(N); npos = rfl(npos); flag = rflp(flag); dyn = rfl(dyn);
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   // wave 0's running pivot scale and count of regularised pivots
-  float pmax = 0.f, lmax = 0.f;
+  float pmax = 0.f, pmaxh = 0.f, lmax = 0.f;
   int nreg = 0;
   if (tid == 0) { flag[0] = 0; flag[2] = 0; }
   if (wid == 0) {
-    const bool fail = factor_panel<RPL>(M, N, npos, 0, dyn, pmax, nreg, lmax);
+    const bool fail = factor_panel<RPL>(M, N, npos, 0, dyn, pmax, pmaxh, nreg, lmax);
     if (fail && lane == 0) flag[0] = 1;
   }
   __syncthreads();
@@ -695,7 +705,7 @@ QPK_PHASE bool signed_cholesky(MF *M, int N, int npos, li *flag, bool dyn) {
     __syncthreads();
     // (2) wave 0: factor the next panel; waves 1..: rest of the update
     if (wid == 0) {
-      const bool fail = factor_panel<RPL>(M, N, npos, r0, dyn, pmax, nreg, lmax);
+      const bool fail = factor_panel<RPL>(M, N, npos, r0, dyn, pmax, pmaxh, nreg, lmax);
       if (fail && lane == 0) flag[0] = 1;
     } else {
       const int r1 = r0 + kNB, R1 = N - r1;
@@ -716,6 +726,7 @@ QPK_PHASE bool signed_cholesky(MF *M, int N, int npos, li *flag, bool dyn) {
     // with regularised pivots, entries of L far beyond the scale sqrt(pmax)
     // of a stable factor mean the replaced pivots amplified rounding errors:
     // report a failure so the caller factors again with a uniform floor
+    pmax = fmaxf(pmax, pmaxh);
     if (lane == 0 && nreg > 0 && !(lmax <= kGrowthMax * sqrtf(pmax))) flag[0] = 1;
   }
   if (tid == 0) {

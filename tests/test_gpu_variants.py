@@ -7,7 +7,8 @@ is the smallest random feasible shape whose plan lands on one of the 18
 reachable configurations (the plan is asserted, so the case keeps covering
 the configuration it names).  For QP 0 of each batch: the solution entry by
 entry (x, s, y, z), then the relaxed point and all six gradient blocks,
-with the tolerances of tests/parity.py.
+with the tolerances of tests/parity.py.  Then rescaled inputs (Q, G or q
+multiplied by powers of ten): every QP converges and two match the oracle.
 """
 import numpy as np
 import pytest
@@ -77,3 +78,35 @@ def test_kernel_configuration_vs_oracle(key):
     worst = max(worst, pt.check_point(f"{key} relaxed QP 0", P, 0, g["relaxed"], rr, tol=1e-6))
     worst = max(worst, pt.check_grads(f"{key} QP 0", g, 0, ref))
     print(f"  iters {sol['iters'].tolist()} worst entry at {worst:.2f} of its bound", flush=True)
+
+
+# Rescaled inputs: Q multiplied by 1e3 moves the border's pivots (of order
+# |A_j|^2 / |Q|) far below the H block's, which each block's own pivot
+# scale in the regularisation test keeps from being taken for numerical
+# zeros; G (with h) by 1e-2 and q by 1e3 stress the same scales.
+RESCALED = [
+    ((5, 0, 4), "Q", 1e3),
+    ((50, 100, 10), "Q", 1e3),
+    ((20, 400, 2), "Q", 1e3),
+    ((12, 40, 11), "G", 1e-2),
+    ((150, 300, 15), "q", 1e3),
+]
+
+
+@pytest.mark.parametrize("case", RESCALED, ids=lambda c: f"{c[0]}_{c[1]}x{c[2]:g}")
+def test_rescaled_inputs_vs_oracle(case):
+    import paper_2605_17913_amd as qpx
+    (n, m, p), which, f = case
+    print(f"rescaled {which} x {f:g}: n={n} m={m} p={p} B=4", flush=True)
+    P = qpgen.random_feasible(4, n, m, p, seed=1000 + n + m + p)
+    getattr(P, which)[...] *= np.float32(f)
+    if which == "G":  # the planted point stays strictly feasible
+        P.h[...] *= np.float32(f)
+    sol = pt.npd(qpx.solve(*pt.to_dev(P)))
+    st = pt.outcome(sol["status"])
+    assert np.all(st == 0), (case, st.tolist(), sol["iters"].tolist())
+    for i in (0, 1):
+        r = implicit.solve_qp(*P.one(i), tol=1e-11, max_iter=300)
+        assert r.status == implicit.CONVERGED
+        worst = pt.check_point(f"{case} QP {i}", P, i, sol, r)
+        print(f"  QP {i}: worst entry at {worst:.2f} of its bound", flush=True)
