@@ -566,9 +566,10 @@ QPD bool panel_sweep(MF *M, int N, int npos, int k0, int kb, int gact, bool dyn,
       // row k0+jj is in lane jj of chunk 0
       const float sg = (k0 + jj) < npos ? 1.f : -1.f;
       // the border's pivots (its Schur complement, of order |C_j|^2 / |H|
-      // plus the diagonal Dl) are tested against the border's own largest
-      // pivot: at the first border column the running maximum restarts
-      // (the H block's is kept in pmaxh)
+      // plus the diagonal Dl, with the rows equilibrated: border_exponent)
+      // are tested against the border's own largest pivot: at the first
+      // border column the running maximum restarts (the H block's is kept
+      // in pmaxh)
       if (k0 + jj == npos) {
         pmaxh = pmax;
         pmax = 0.f;
@@ -668,6 +669,72 @@ QPD bool factor_panel(MF *M, int N, int npos, int k0, bool dyn, float &pmax, flo
   return fail;
 }
 
+// Equilibration of the border for the pivot tests.  The regularisation
+// test compares each border pivot with the largest border pivot accepted so
+// far, so a border that mixes rows of very different norms (inequality rows
+// of G and equality rows of A in different units) would have the small
+// rows' pivots taken for numerical zeros.  Before the factorisation, border
+// row i (i >= npos) is multiplied by s_i = 2^k_i and its diagonal entry by
+// s_i^2, with k_i = floor((e_max - e_i) / 2), e_i the binary exponent of
+// |C_i|^2 and e_max the largest one (rows within about a factor of two in
+// norm of the largest keep s_i = 1); after it, row i of the factor is
+// divided by s_i.  The scalings are powers of two and so exact: the result
+// is bit for bit the factor of the unscaled matrix wherever the scaled
+// tests decide as the unscaled ones would, and the factor with the scaled
+// tests' replacements otherwise.  The assembly computes e_i while it copies
+// the border rows and keeps it in the first float of row i's padding, the
+// per-wave maxima of e in flag[8 ..] (at most 8 waves).
+constexpr int kNoExp = -1000;
+QPD int mpad(int i) { return moff(i) + 16 * ((i >> 4) + 1); }
+template <int T>
+QPD int border_emax(const li *flag) {
+  int e = kNoExp;
+#pragma unroll
+  for (int w = 0; w < T / 64; ++w) e = max(e, flag[8 + w]);
+  return e;
+}
+template <class MF>
+QPD int border_shift(const MF *M, int i, int emax) {
+  const int e = __float_as_int(M[mpad(i)]);
+  return e == kNoExp ? 0 : min((emax - e) >> 1, 30);
+}
+// Exponent e_i of the squared norm ss (the same in all 16 lanes of row i's
+// group) into row i's padding (if store), and the thread's running maximum.
+template <class MF>
+QPD void border_exponent(MF *M, int i, bool store, int sub, float ss, float &el) {
+  ss = row_bfly<OpSum>(ss);
+  int e = kNoExp;
+  if (ss > 0.f && ss <= FLT_MAX) (void)frexpf(ss, &e);
+  if (store) {
+    if (sub == 0) M[mpad(i)] = __int_as_float(e);
+    el = fmaxf(el, (float)e);
+  }
+}
+// Per-wave maxima of the exponents into flag[8 ..]; read after a barrier.
+template <int T>
+QPD void border_exponents_done(float el, li *flag) {
+  static_assert(T / 64 <= 8, "per-wave exponent slots");
+  el = wave_bfly<OpMax>(el);
+  if ((threadIdx.x & 63) == 0) flag[8 + (threadIdx.x >> 6)] = (int)el;
+}
+// Wave 0: f(i, k_i) for every border row i with k_i > 0, in row order (a
+// lane per row reads the exponents; the rows to rescale, usually few, are
+// then taken one at a time by the whole wave).
+template <class MF, class F>
+QPD void border_shifted_rows(const MF *M, int N, int npos, int emax, F &&f) {
+  const int lane = threadIdx.x & 63, K = N - npos;
+  for (int k0 = 0; k0 < K; k0 += 64) {
+    const int k = k0 + lane;
+    const int sh = k < K ? border_shift(M, npos + k, emax) : 0;
+    unsigned long long b = __ballot(sh > 0);
+    while (b) {
+      const int l = __builtin_ctzll(b);
+      b &= b - 1;
+      f(npos + k0 + l, __builtin_amdgcn_readlane(sh, l));
+    }
+  }
+}
+
 // In-place M = L diag(sg) L' (lower triangle, packed-blocked layout),
 // sg_j = +1 for j < npos, -1 otherwise.  Blocked right-looking with one
 // panel of lookahead: after panel k is factored, all waves first apply it
@@ -677,9 +744,11 @@ QPD bool factor_panel(MF *M, int N, int npos, int k0, bool dyn, float &pmax, flo
 // strict upper part of each row's last 16-column segment is left at exact
 // zeros.  Returns false (uniformly) if a pivot sg_j * a_jj is not a positive
 // finite number.  With dyn, numerically zero pivots are regularised (see
-// factor_panel) and flag[2] receives their count.  flag[0] is the failure
-// flag, flag[4] the largest accepted pivot (float bits); flag[1] and flag[3]
-// are left alone.  RPL = rows per lane, >= ceil(N / 64).
+// factor_panel; the tests see the border equilibrated, border_exponent) and
+// flag[2] receives their count.  flag[0] is the failure flag, flag[4] the
+// largest accepted pivot (float bits, the border's in equilibrated units);
+// flag[1] and flag[3] are left alone, flag[8 ..] is scratch.  RPL = rows
+// per lane, >= ceil(N / 64).
 template <int T, int RPL, class MF>
 QPK_PHASE bool signed_cholesky(MF *M, int N, int npos, li *flag, bool dyn) {
   M = rflp(M); N = rfl(N); npos = rfl(npos); flag = rflp(flag); dyn = rfl(dyn);
@@ -688,7 +757,22 @@ QPK_PHASE bool signed_cholesky(MF *M, int N, int npos, li *flag, bool dyn) {
   float pmax = 0.f, pmaxh = 0.f, lmax = 0.f;
   int nreg = 0;
   if (tid == 0) { flag[0] = 0; flag[2] = 0; }
+  // with the pivot tests on, they see the border equilibrated: wave 0
+  // scales the rows before its first panel (the other waves first read
+  // them after the barrier that follows it) and takes the scaling back out
+  // of the factor at the end (see border_exponent)
+  const bool eq = dyn && N > npos;
+  const int emax = eq ? border_emax<T>(flag) : 0;
   if (wid == 0) {
+    if (eq) {
+      border_shifted_rows(M, N, npos, emax, [&](int i, int sh) {
+        MF *row = M + moff(i);
+        const float s = ldexpf(1.f, sh);
+        for (int j = lane; j < npos; j += 64) row[j] *= s;
+        if (lane == 0) row[i] *= s * s;  // the border block is diagonal here
+      });
+      __threadfence_block();  // the panel's loads see the scaled rows
+    }
     const bool fail = factor_panel<RPL>(M, N, npos, 0, dyn, pmax, pmaxh, nreg, lmax);
     if (fail && lane == 0) flag[0] = 1;
   }
@@ -728,6 +812,13 @@ QPK_PHASE bool signed_cholesky(MF *M, int N, int npos, li *flag, bool dyn) {
     // report a failure so the caller factors again with a uniform floor
     pmax = fmaxf(pmax, pmaxh);
     if (lane == 0 && nreg > 0 && !(lmax <= kGrowthMax * sqrtf(pmax))) flag[0] = 1;
+    if (eq) {
+      border_shifted_rows(M, N, npos, emax, [&](int i, int sh) {
+        MF *row = M + moff(i);
+        const float r = ldexpf(1.f, -sh);
+        for (int j = lane; j <= i; j += 64) row[j] *= r;
+      });
+    }
   }
   if (tid == 0) {
     flag[2] = nreg;
@@ -1561,14 +1652,30 @@ QPK_PHASE void assemble(CT &Cin_, int nb, int ne, const lf *wts, bool bounded, f
   }
   }
   __syncthreads();
-  // border rows: [C | -Dl (lower part)].  C = [G_B; A] as row copies with
-  // several loads in flight, then the lower triangle of the diagonal block.
+  // border rows: [C | -Dl (lower part)].  C = [G_B; A] copied by 16 lanes
+  // per row, which also take each row's squared norm for the border
+  // equilibration of the factorisation (border_exponent); then the lower
+  // triangle of the diagonal block.
   const int K = nb + p;
-#pragma unroll 4
-  for (int e = tid; e < K * n; e += T) {
-    const int k = e / n, col = e - k * n;
-    M[moff(n + k) + col] =
-        k < nb ? C.G[(size_t)C.bidx[k] * n + col] : C.A[(size_t)(k - nb) * n + col];
+  {
+    constexpr int NG = T / 16;
+    const int sub = tid & 15, grp = tid >> 4;
+    float el = (float)kNoExp;
+    for (int k0 = 0; k0 < K; k0 += NG) {
+      // groups past the last row repeat it (the row reduction needs all 16
+      // lanes) and store nothing
+      const int k = k0 + grp, kc = min(k, K - 1);
+      const gf *src = kc < nb ? C.G.get() + (size_t)C.bidx[kc] * n : C.A.get() + (size_t)(kc - nb) * n;
+      auto *row = M + moff(n + kc);
+      float ss = 0.f;
+      for (int j = sub; j < n; j += 16) {
+        const float v = src[j];
+        if (k < K) row[j] = v;
+        ss = fmaf(v, v, ss);
+      }
+      border_exponent(M, n + kc, k < K, sub, ss, el);
+    }
+    border_exponents_done<T>(el, C.iflag);
   }
   for (int e = tid; e < K * K; e += T) {
     const int k = e / K, l = e - k * K;

@@ -7,8 +7,9 @@ is the smallest random feasible shape whose plan lands on one of the 18
 reachable configurations (the plan is asserted, so the case keeps covering
 the configuration it names).  For QP 0 of each batch: the solution entry by
 entry (x, s, y, z), then the relaxed point and all six gradient blocks,
-with the tolerances of tests/parity.py.  Then rescaled inputs (Q, G or q
-multiplied by powers of ten): every QP converges and two match the oracle.
+with the tolerances of tests/parity.py.  Then rescaled inputs (Q, G, A or
+q multiplied by powers of ten): every QP converges and two match the
+oracle.
 """
 import numpy as np
 import pytest
@@ -83,13 +84,21 @@ def test_kernel_configuration_vs_oracle(key):
 # Rescaled inputs: Q multiplied by 1e3 moves the border's pivots (of order
 # |A_j|^2 / |Q|) far below the H block's, which each block's own pivot
 # scale in the regularisation test keeps from being taken for numerical
-# zeros; G (with h) by 1e-2 and q by 1e3 stress the same scales.
+# zeros; G (with h) by 1e-2 and q by 1e3 stress the same scales.  G by 1e2
+# or A (with b) by 1e-2 puts inequality and equality rows of norms 1e4
+# apart in one border, whose equilibration keeps the equality rows' pivots
+# from being taken for numerical zeros (without it most of these QPs ended
+# at the iteration limit).
 RESCALED = [
     ((5, 0, 4), "Q", 1e3),
     ((50, 100, 10), "Q", 1e3),
     ((20, 400, 2), "Q", 1e3),
     ((12, 40, 11), "G", 1e-2),
     ((150, 300, 15), "q", 1e3),
+    ((50, 100, 10), "G", 1e2),
+    ((150, 300, 15), "G", 1e2),
+    ((20, 400, 2), "G", 1e2),
+    ((12, 40, 11), "A", 1e-2),
 ]
 
 
@@ -102,6 +111,8 @@ def test_rescaled_inputs_vs_oracle(case):
     getattr(P, which)[...] *= np.float32(f)
     if which == "G":  # the planted point stays strictly feasible
         P.h[...] *= np.float32(f)
+    if which == "A":  # and on the equality constraints
+        P.b[...] *= np.float32(f)
     sol = pt.npd(qpx.solve(*pt.to_dev(P)))
     st = pt.outcome(sol["status"])
     assert np.all(st == 0), (case, st.tolist(), sol["iters"].tolist())
