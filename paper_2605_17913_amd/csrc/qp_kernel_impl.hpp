@@ -2230,7 +2230,11 @@ QPK_PHASE int newton_bounded(CT &Cin_, float &kappa, int kt_mode, float sigma, f
   // step on (x, y, v, kappa), then retract z, s
   for (int i = tid; i < n; i += T) C.x[i] += alpha * fmaf(kt, C.u1[i], C.u0[i]);
   for (int k = tid; k < p; k += T) C.y[k] += alpha * fmaf(kt, C.u1[n + nb + k], C.u0[n + nb + k]);
-  const float knew = kappa + alpha * dk;
+  // kappa + alpha (kt - kappa) lies between kt and kappa, but with alpha = 1
+  // and kt below kappa's rounding unit the sum rounds to exactly zero: z of
+  // every inactive row would then be 0 and the next centering would divide
+  // by kappa = 0.  Held at the bound the step cannot cross.
+  const float knew = fmaxf(kappa + alpha * dk, fminf(kt, kappa));
   for (int i = tid; i < m; i += T) {
     const float vn = C.v[i] + alpha * fmaf(kt, C.dv1[i], C.dv0[i]);
     C.v[i] = vn;
